@@ -1,0 +1,273 @@
+/*
+ * pila.h - C ABI of the MI355X (gfx950) library for simulated annealing
+ * tomography (SAT) with a pre-calculated intersection lengths array (PILA).
+ *
+ * Method: N. T. Vo, M. B. H. Breese, H. O. Moser, "Feasibility of Simulated
+ * Annealing Tomography" (arXiv 1411.4622).  Each entry point below names the
+ * passage of the paper that defines the operation it performs.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int32 status (PILA_OK or a negative PILA_E*
+ *   code).  Nothing aborts or exits; pila_last_error() returns a message for
+ *   the last failure on the calling thread.
+ * - Pointers prefixed d_ (and the device arrays inside pila_csr) are device
+ *   memory on the current HIP device, allocated and owned by the caller.
+ *   Pointers prefixed h_ and the arrays inside pila_geom are host memory,
+ *   read or written only during the call.
+ * - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *   Device work is enqueued on it asynchronously unless a function says
+ *   it synchronises (it then waits for that stream only).
+ * - Images are N x N row-major FP64, row 0 at the top: pixel (i, j) covers
+ *   x in [j - N/2, j - N/2 + 1), y in [N/2 - 1 - i, N/2 - i), p = i*N + j.
+ * - Sinograms are U x K row-major FP64, angle-major: ray g = u*K + k is the
+ *   line x cos(a_u) + y sin(a_u) = k - (K-1)/2 (unit bin spacing, rays at
+ *   bin centres).  Angles are given in degrees; multiples of 90 degrees use
+ *   exact (cos, sin).
+ * - A ray lying on a pixel edge (axis-parallel rays) belongs to the pixel
+ *   whose half-open interval contains it; intersection lengths <= 1e-9
+ *   (corner touches) are not stored.
+ */
+#ifndef PILA_H
+#define PILA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PILA_OK 0
+#define PILA_EINVAL (-1)    /* bad argument (sizes, NULL pointers, non-finite input) */
+#define PILA_ENOMEM (-2)    /* workspace or memory budget too small */
+#define PILA_EHIP (-3)      /* HIP runtime error; the message carries its text */
+#define PILA_ESIZE (-4)     /* buffer size does not match a previous phase */
+#define PILA_ECANCELED (-5) /* request cancelled */
+#define PILA_EBUSY (-6)     /* not admissible now; retry later */
+#define PILA_ENOTFOUND (-7) /* unknown ticket */
+
+/* storage / arithmetic types */
+#define PILA_F64 0
+#define PILA_F32 1
+
+/* ------------------------------------------------------------------------ */
+/* Geometry and the PILA (section II-B, Eq. 5)                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct pila_geom {
+    int32_t n;                /* image side N (N x N unit pixels), >= 1 */
+    int32_t n_angles;         /* U, >= 1 */
+    int32_t n_bins;           /* K, detector bins at unit spacing, >= 1 */
+    int32_t len_dtype;        /* PILA_F64 or PILA_F32: storage type of lengths */
+    const double* angles_deg; /* host [U], finite */
+    const uint8_t* mask;      /* host [N*N], nonzero = support pixel; NULL = all */
+} pila_geom;
+
+/*
+ * A built PILA.  All arrays are caller-allocated device memory.
+ *   row_ptr [N*N+1]  pixel-major CSR offsets (int64)
+ *   col     [nnz]    ray index g = u*K + k, strictly ascending within a row
+ *   len     [nnz]    intersection length (double or float per len_dtype)
+ *   support [n_support] support pixel indices, ascending
+ *   trig    [2*U]    (cos, sin) of every angle, as used for the build
+ *   t_row_ptr [U*K+1], t_col [nnz], t_len [nnz]: the same entries ray-major
+ *                    (t_col = pixel index, ascending within a ray)
+ * Rows of pixels outside the mask are empty.
+ */
+typedef struct pila_csr {
+    int64_t nnz;       /* out of phase 1 */
+    int32_t n_support; /* out of phase 1 */
+    int32_t reserved;
+    int64_t* row_ptr;
+    int32_t* col;
+    void* len;
+    int32_t* support;
+    double* trig;
+    int64_t* t_row_ptr;
+    int32_t* t_col;
+    void* t_len;
+} pila_csr;
+
+/*
+ * pila_build - intersection lengths of every support pixel with every ray
+ * (section II-B: per pixel, the detector positions and lengths at each
+ * angle, Eq. 5), stored pixel-major and ray-major.
+ *
+ * Two phases.  Phase 1 (csr->col == NULL): needs csr->row_ptr, csr->trig
+ * and csr->t_row_ptr; fills them, sets csr->nnz and csr->n_support, and
+ * synchronises the stream.  Phase 2 (csr->col != NULL): needs every array,
+ * sized from phase 1; row_ptr/t_row_ptr must still hold phase 1's output.
+ * Fills col, len, support, t_col, t_len and synchronises.
+ * Errors: EINVAL for n, U or K < 1, a non-finite angle, a NULL array, or
+ * len_dtype not PILA_F64/PILA_F32; ESIZE when phase 2's row_ptr total does
+ * not equal csr->nnz; EHIP on a runtime failure.
+ */
+int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream);
+
+/*
+ * pila_forward - Eq. 1 for every ray: d_out[g] = sum over pixels of
+ * l(p, g) * d_image[p], through the ray-major PILA (FP64 accumulation).
+ * d_image [N*N] FP64, d_out [U*K] FP64.  Deterministic.  Asynchronous.
+ */
+int32_t pila_forward(const pila_geom* geom, const pila_csr* csr, const double* d_image,
+                     double* d_out, void* stream);
+
+/*
+ * pila_backproject - transpose of Eq. 1: d_out[p] = sum over the rays
+ * crossing p of l(p, g) * d_sino[g], through the pixel-major PILA (FP64
+ * accumulation).  d_sino [U*K], d_out [N*N].  Deterministic.  Asynchronous.
+ */
+int32_t pila_backproject(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                         double* d_out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Simulated annealing (section II-A Steps 1-4, II-B Eq. 6-7, III Eq. 8,    */
+/* III-B best of multiple estimates)                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct sat_params {
+    uint64_t seed;       /* Philox key word 0 */
+    uint64_t chain_id;   /* Philox key word 1 */
+    int64_t n_steps;     /* total steps (each: m_cand estimates, one update) */
+    int32_t n_stages;    /* N of Eq. 2: temperature stages, >= 1 */
+    int32_t m_cand;      /* N_e of the BoME strategy, 1..64 */
+    double T0, TN;       /* Eq. 2 end points; T0 <= 0 selects Eq. 8 */
+    int32_t q_auto;      /* Q of Eq. 8 (uphill estimates averaged), >= 1 */
+    int32_t precision;   /* PILA_F64 or PILA_F32 residual sinogram */
+    double tn_ratio;     /* T_N = T_0 / tn_ratio when Eq. 8 is used */
+    double delta_max;    /* Eq. 3 step: change uniform in [-delta_max, delta_max) */
+    double f_min, f_max; /* value range; a new value is clamped into it */
+    int64_t resync_every; /* FP32: FP64 recomputation of the residual after
+                             this many accepted nonzero changes; 0 = never */
+} sat_params;
+
+typedef struct sat_stats {
+    int64_t steps, accepts, accepts_nonzero;
+    int32_t resyncs;
+    int32_t status;         /* PILA_OK, or PILA_EINVAL when Eq. 8 failed */
+    double T0_used, TN_used;
+    double sse_final;       /* running sum of squared residuals at the end */
+    double cost_final;      /* Eq. 4 of the final image (running value) */
+    double max_drift_r;     /* FP32: max |r32 - r64| seen at a resync */
+    double max_drift_sse;   /* FP32: max relative |SSE_run - SSE64| at a resync */
+} sat_stats;
+
+/* Optional per-step record, device arrays of n_steps elements (each may be
+ * NULL): chosen estimate, acceptance, and the cost change Delta C. */
+typedef struct sat_trace {
+    int32_t* m_star;
+    uint8_t* accept;
+    double* dC;
+} sat_trace;
+
+/*
+ * sat_workspace_size - device workspace bytes that sat_run needs.
+ */
+int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes);
+
+/*
+ * sat_run - one SAT chain.  From the starting image d_image (N*N, updated
+ * in place) and the measured sinogram d_sino (Pm, U*K):
+ *   r = A f - Pm and its sum of squares (Eq. 1, Eq. 4);
+ *   T0/TN given, or from Eq. 8 (estimates from the starting image,
+ *   Philox counter (q, 0, 2, 0));
+ *   for step s: m_cand estimates (Philox4x64-10, key (seed, chain_id),
+ *   counter (s, m, 0, 0)): pixel uniform over the support, change uniform
+ *   in [-delta_max, delta_max), new value clamped to [f_min, f_max]; each
+ *   scored by the change of the squared-residual sum over its PILA row
+ *   (Eq. 7); the first minimum is kept (BoME); accepted when its cost
+ *   change Delta C <= 0 or N1 < exp(-Delta C / T) (Step 4; N1 from counter
+ *   (s, 0, 1, 0)); T from Eq. 2 at stage floor(s * n_stages / n_steps);
+ *   on acceptance the residual is updated over the row (Eq. 6).
+ * precision PILA_F64 needs len_dtype PILA_F64; PILA_F32 needs PILA_F32
+ * (then the residual and the row sums are FP32, the cost total FP64, and the
+ * residual is recomputed in FP64 every resync_every nonzero accepts).
+ * h_stats (nullable) receives the chain's statistics: the call then
+ * synchronises.  trace (nullable, host struct of device arrays) records
+ * every step.  Errors: EINVAL (bad sizes/params, dtype mismatch, empty
+ * support), ENOMEM (ws_bytes below sat_workspace_size), EHIP.
+ */
+int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                sat_stats* h_stats, const sat_trace* trace, void* stream);
+
+/* One independent chain of a batch. */
+typedef struct sat_job {
+    const pila_geom* geom;
+    const pila_csr* csr;
+    const double* d_sino;
+    double* d_image;
+    sat_params params;
+} sat_job;
+
+/* Launch shape of the batched kernel (nullable: library default). */
+typedef struct sat_launch {
+    int32_t waves_per_chain; /* 1, 2, 4, 8 or 16 wavefronts per chain */
+    int32_t chains_per_cu;   /* resident chains per compute unit */
+    int32_t lds_residual;    /* 1: keep a chain's residual in LDS when it fits */
+    int32_t reserved;
+} sat_launch;
+
+/*
+ * sat_batch_workspace_size / sat_run_batch - many independent chains (one
+ * per slice) in one persistent launch: one workgroup runs one chain at a
+ * time and takes the next chain from a device ticket counter.  Each chain
+ * computes exactly what sat_run computes for its job, independently of the
+ * other jobs and of the launch shape's chain placement.  h_stats [n_jobs]
+ * (nullable) makes the call synchronise.
+ */
+int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs, size_t* bytes);
+int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch, void* d_ws,
+                      size_t ws_bytes, sat_stats* h_stats, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* SIRT with exact lengths (section III-D, Eq. 10-11)                        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct sirt_params {
+    int32_t n_iter;
+    int32_t reserved;
+    double lambda; /* relaxation; 1 is the unrelaxed update */
+} sirt_params;
+
+/* sirt_workspace_size - device workspace bytes that sirt_run needs. */
+int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params* params, size_t* bytes);
+
+/*
+ * sirt_run - simultaneous SIRT driven by the PILA: factor matrix
+ * W_g = sum over support pixels of l(p, g)^2 (section III-D); each
+ * iteration res = Pm - A f (ray-major PILA), then every support pixel moves
+ * by (lambda / U) * sum over its row of l * res_g / W_g (Eq. 10-11 summed
+ * over all rays crossing the pixel).  d_image (N*N) in: start, out: result.
+ * h_cost (nullable, n_iter doubles) receives Eq. 4 of the image entering
+ * each iteration; the call then synchronises.
+ */
+int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                 const sirt_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                 double* h_cost, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Device information and errors                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct pila_device_info {
+    int32_t cu_count;
+    int32_t lds_per_block;   /* bytes */
+    int32_t clock_khz;
+    int32_t warp_size;
+    size_t hbm_bytes;
+    char name[64];
+} pila_device_info;
+
+int32_t pila_get_device_info(pila_device_info* info);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* pila_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PILA_H */

@@ -60,6 +60,10 @@ def _load():
     lib.or_rays.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P]
     lib.or_rays.restype = C.c_int64
     lib.or_pila_from_rays.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P]
+    lib.or_trace_ray.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, P, P, P]
+    lib.or_trace_ray.restype = C.c_int32
+    lib.or_pixel_row.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, C.c_int32, P, P]
+    lib.or_pixel_row.restype = C.c_int32
     lib.or_forward.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P]
     lib.or_backward.argtypes = [C.c_int32, P, P, P, P, P]
     lib.or_temperature.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double]
@@ -119,6 +123,25 @@ def pila(N: int, U: int, K: int, angles, mask=None, with_rays: bool = False):
     if with_rays:
         return (row_ptr, col, plen), (off, pix, ln)
     return row_ptr, col, plen
+
+
+def trace_ray(N: int, K: int, deg: float, k: int, mask=None):
+    """One ray traced on its own (Siddon): (pixels in trace order, lengths)."""
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    pix = np.zeros(2 * N + 8, dtype=np.int32)
+    ln = np.zeros(2 * N + 8, dtype=np.float64)
+    n = _load().or_trace_ray(N, K, float(deg), int(k), _p(m), _p(pix), _p(ln))
+    return pix[:n].copy(), ln[:n].copy()
+
+
+def pixel_row(N: int, U: int, K: int, angles, p: int, mask=None):
+    """PILA row of one pixel (Eq. 5), traced ray by ray: (g ascending, lengths)."""
+    a = np.ascontiguousarray(angles, dtype=np.float64)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    g = np.zeros(4 * U + 8, dtype=np.int32)
+    ln = np.zeros(4 * U + 8, dtype=np.float64)
+    n = _load().or_pixel_row(N, U, K, _p(a), _p(m), int(p), _p(g), _p(ln))
+    return g[:n].copy(), ln[:n].copy()
 
 
 def forward(N: int, U: int, K: int, csr, f) -> np.ndarray:

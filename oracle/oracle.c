@@ -118,18 +118,12 @@ void or_trig(int32_t U, const double* deg, double* cs)
 
 /* Column of an image x coordinate, row of an image y coordinate (pixel
  * (i, j) covers x in [j - N/2, j - N/2 + 1) and y in [N/2-1-i, N/2-i)). */
-static long col_of(double x, double h) { return (long)floor(x + h); }
-static long row_of(double y, double h) { return -(long)floor(y - h + 1.0); }
+static long col_of(long double x, long double h) { return (long)floorl(x + h); }
+static long row_of(long double y, long double h) { return -(long)floorl(y - h + 1.0L); }
 
-typedef struct {
-    int32_t* pix;
-    double* len;
-    int cap;
-} ray_out;
-
-static int cmp_double(const void* a, const void* b)
+static int cmp_ld(const void* a, const void* b)
 {
-    double x = *(const double*)a, y = *(const double*)b;
+    long double x = *(const long double*)a, y = *(const long double*)b;
     return (x > y) - (x < y);
 }
 
@@ -141,14 +135,20 @@ static int cmp_double(const void* a, const void* b)
  * (only possible when it is axis-parallel) belongs to the pixel whose
  * half-open interval contains it.  Pieces of the same pixel are summed and
  * lengths <= OR_TAU dropped (corner grazes).  Returns the pixel count.
- * ts must hold at least 2N + 4 doubles.
+ *
+ * The trace runs in x87 extended precision: a piece cut from a pixel corner
+ * by a ray at a small angle alpha to a grid line has a length that moves by
+ * about 1 / (|cos alpha| |sin alpha|) per unit shift of the ray, so FP64
+ * crossing parameters of size ~N would leave errors above 1e-12 in the
+ * lengths of large grids.  Results are rounded to double at the end.
+ * ts must hold at least 2N + 4 entries.
  */
-static int siddon_ray(int N, double c, double sn, double s, const uint8_t* mask, int32_t* pix,
-                      double* len, double* ts)
+static int siddon_ray(int N, double c_, double sn_, double s_, const uint8_t* mask, int32_t* pix,
+                      double* len, long double* ts, long double* acc)
 {
-    const double h = N / 2.0;
+    const long double h = N / 2.0L, c = c_, sn = sn_, s = s_;
     int n = 0;
-    if (sn == 0.0) { /* vertical ray x = s * c */
+    if (sn == 0.0L) { /* vertical ray x = s * c */
         long j = col_of(s * c, h);
         if (j < 0 || j >= N) return 0;
         for (int i = 0; i < N; ++i) {
@@ -160,7 +160,7 @@ static int siddon_ray(int N, double c, double sn, double s, const uint8_t* mask,
         }
         return n;
     }
-    if (c == 0.0) { /* horizontal ray y = s * sn */
+    if (c == 0.0L) { /* horizontal ray y = s * sn */
         long i = row_of(s * sn, h);
         if (i < 0 || i >= N) return 0;
         for (int j = 0; j < N; ++j) {
@@ -173,29 +173,29 @@ static int siddon_ray(int N, double c, double sn, double s, const uint8_t* mask,
         return n;
     }
     /* point on the ray: (s c - t sn, s sn + t c) */
-    const double x0 = s * c, y0 = s * sn;
-    double tx1 = (x0 + h) / sn, tx2 = (x0 - h) / sn;
-    double ty1 = (-h - y0) / c, ty2 = (h - y0) / c;
-    double tlo = fmax(fmin(tx1, tx2), fmin(ty1, ty2));
-    double thi = fmin(fmax(tx1, tx2), fmax(ty1, ty2));
+    const long double x0 = s * c, y0 = s * sn;
+    long double tx1 = (x0 + h) / sn, tx2 = (x0 - h) / sn;
+    long double ty1 = (-h - y0) / c, ty2 = (h - y0) / c;
+    long double tlo = fmaxl(fminl(tx1, tx2), fminl(ty1, ty2));
+    long double thi = fminl(fmaxl(tx1, tx2), fmaxl(ty1, ty2));
     if (!(thi > tlo)) return 0;
     int nt = 0;
     ts[nt++] = tlo;
     ts[nt++] = thi;
     for (int j = 0; j <= N; ++j) {
-        double t = (x0 - (-h + j)) / sn;
+        long double t = (x0 - (-h + j)) / sn;
         if (t > tlo && t < thi) ts[nt++] = t;
     }
     for (int i = 0; i <= N; ++i) {
-        double t = ((-h + i) - y0) / c;
+        long double t = ((-h + i) - y0) / c;
         if (t > tlo && t < thi) ts[nt++] = t;
     }
-    qsort(ts, (size_t)nt, sizeof(double), cmp_double);
+    qsort(ts, (size_t)nt, sizeof(long double), cmp_ld);
     int last = -1;
     for (int q = 0; q + 1 < nt; ++q) {
-        double d = ts[q + 1] - ts[q];
-        if (!(d > 0.0)) continue;
-        double tm = 0.5 * (ts[q] + ts[q + 1]);
+        long double d = ts[q + 1] - ts[q];
+        if (!(d > 0.0L)) continue;
+        long double tm = 0.5L * (ts[q] + ts[q + 1]);
         long j = col_of(x0 - tm * sn, h);
         long i = row_of(y0 + tm * c, h);
         if (j < 0) j = 0;
@@ -204,10 +204,10 @@ static int siddon_ray(int N, double c, double sn, double s, const uint8_t* mask,
         if (i >= N) i = N - 1;
         int p = (int)i * N + (int)j;
         if (p == last) {
-            len[n - 1] += d;
+            acc[n - 1] += d;
         } else {
             pix[n] = p;
-            len[n] = d;
+            acc[n] = d;
             ++n;
             last = p;
         }
@@ -215,9 +215,10 @@ static int siddon_ray(int N, double c, double sn, double s, const uint8_t* mask,
     /* drop grazes and masked pixels, keep trace order */
     int m = 0;
     for (int q = 0; q < n; ++q) {
-        if (len[q] > OR_TAU && (!mask || mask[pix[q]])) {
+        double l = (double)acc[q];
+        if (l > OR_TAU && (!mask || mask[pix[q]])) {
             pix[m] = pix[q];
-            len[m] = len[q];
+            len[m] = l;
             ++m;
         }
     }
@@ -234,15 +235,16 @@ int64_t or_rays(int32_t N, int32_t U, int32_t K, const double* deg, const uint8_
                 int32_t* cnt, const int64_t* off, int32_t* pix, double* len)
 {
     double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)U);
-    double* ts = (double*)malloc(sizeof(double) * (2 * (size_t)N + 8));
-    int32_t* bp = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)N + 8);
-    double* bl = (double*)malloc(sizeof(double) * 2 * (size_t)N + 8);
+    long double* ts = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    long double* acc = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    int32_t* bp = (int32_t*)malloc(sizeof(int32_t) * (2 * (size_t)N + 8));
+    double* bl = (double*)malloc(sizeof(double) * (2 * (size_t)N + 8));
     or_trig(U, deg, cs);
     int64_t total = 0;
     for (int u = 0; u < U; ++u) {
         for (int k = 0; k < K; ++k) {
             double s = k - (K - 1) / 2.0;
-            int n = siddon_ray(N, cs[2 * u], cs[2 * u + 1], s, mask, bp, bl, ts);
+            int n = siddon_ray(N, cs[2 * u], cs[2 * u + 1], s, mask, bp, bl, ts, acc);
             int64_t g = (int64_t)u * K + k;
             if (pix) {
                 memcpy(pix + off[g], bp, sizeof(int32_t) * (size_t)n);
@@ -255,9 +257,68 @@ int64_t or_rays(int32_t N, int32_t U, int32_t K, const double* deg, const uint8_
     }
     free(cs);
     free(ts);
+    free(acc);
     free(bp);
     free(bl);
     return total;
+}
+
+/* One ray g = u*K + k traced on its own: its pixels (trace order) and
+ * lengths.  pix/len need room for 2N entries.  Returns the count. */
+int32_t or_trace_ray(int32_t N, int32_t K, double deg, int32_t k, const uint8_t* mask,
+                     int32_t* pix, double* len)
+{
+    double cs[2];
+    or_trig(1, &deg, cs);
+    long double* ts = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    long double* acc = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    int n = siddon_ray(N, cs[0], cs[1], k - (K - 1) / 2.0, mask, pix, len, ts, acc);
+    free(ts);
+    free(acc);
+    return n;
+}
+
+/*
+ * PILA row of one pixel (Eq. 5) without building the whole array: every ray
+ * that could reach the pixel (bins within one unit of the projection of the
+ * pixel centre, a superset of its shadow) is traced in full and the pixel's
+ * piece kept.  Entries come out in ascending g.  g/len need room for 4U.
+ */
+int32_t or_pixel_row(int32_t N, int32_t U, int32_t K, const double* deg, const uint8_t* mask,
+                     int32_t p, int32_t* g_out, double* len_out)
+{
+    if (mask && !mask[p]) return 0;
+    double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)U);
+    long double* ts = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    long double* acc = (long double*)malloc(sizeof(long double) * (2 * (size_t)N + 8));
+    int32_t* bp = (int32_t*)malloc(sizeof(int32_t) * (2 * (size_t)N + 8));
+    double* bl = (double*)malloc(sizeof(double) * (2 * (size_t)N + 8));
+    or_trig(U, deg, cs);
+    const double h = N / 2.0;
+    const double xc = (p % N) - h + 0.5, yc = h - 0.5 - (p / N);
+    int32_t n = 0;
+    for (int u = 0; u < U; ++u) {
+        double t0 = xc * cs[2 * u] + yc * cs[2 * u + 1];
+        long k0 = (long)floor(t0 + (K - 1) / 2.0 - 1.0);
+        for (long k = k0; k <= k0 + 3; ++k) {
+            if (k < 0 || k >= K) continue;
+            double s = k - (K - 1) / 2.0;
+            if (fabs(s - t0) > 1.0) continue;
+            int m = siddon_ray(N, cs[2 * u], cs[2 * u + 1], s, mask, bp, bl, ts, acc);
+            for (int q = 0; q < m; ++q)
+                if (bp[q] == p) {
+                    g_out[n] = (int32_t)(u * K + k);
+                    len_out[n] = bl[q];
+                    ++n;
+                }
+        }
+    }
+    free(cs);
+    free(ts);
+    free(acc);
+    free(bp);
+    free(bl);
+    return n;
 }
 
 /*

@@ -1,0 +1,57 @@
+"""GPU parity of PILA-driven SIRT (Eq. 10-11) against the oracle (MI355X)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1411_4622_amd as P
+    P.load()
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return P
+
+
+@pytest.mark.parametrize("N,U,K,lam,iters", [(32, 30, 46, 0.1, 20), (64, 90, 91, 1.0, 10),
+                                             (47, 33, 67, 0.5, 15)])
+def test_sirt_matches_oracle(P, N, U, K, lam, iters):
+    ell = datagen.random_ellipses(N + U, N, 6)
+    sl = datagen.make_slice(N, U, K, ell, masked=True, I0=1e4, noise_seed=5)
+    geom = P.Geometry(N, sl.angles, K, sl.mask, "f64")
+    pl = P.pila_build(geom)
+    img = torch.from_numpy(sl.f0.copy()).cuda()
+    cost = P.sirt_run(pl, torch.from_numpy(sl.sino).cuda(), iters, lam, img)
+    f_g = img.cpu().numpy()
+    csr = oracle.pila(N, U, K, sl.angles, sl.mask)
+    f_o, c_o = oracle.sirt_run(N, U, K, csr, sl.sino, sl.f0, iters, lam)
+    assert np.max(np.abs(f_g - f_o)) <= 1e-10 * max(1.0, np.max(np.abs(f_o)))
+    assert np.max(np.abs(cost - c_o) / c_o) <= 1e-12
+
+
+def test_sirt_f32_lengths_close(P):
+    N, U, K = 64, 60, 91
+    ell = datagen.random_ellipses(8, N, 6)
+    sl = datagen.make_slice(N, U, K, ell, masked=True)
+    out = []
+    for dt in ("f64", "f32"):
+        pl = P.pila_build(P.Geometry(N, sl.angles, K, sl.mask, dt))
+        img = torch.from_numpy(sl.f0.copy()).cuda()
+        P.sirt_run(pl, torch.from_numpy(sl.sino).cuda(), 30, 0.5, img)
+        out.append(img.cpu().numpy())
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-5
+
+
+def test_sirt_zero_iterations(P):
+    N, U, K = 16, 12, 23
+    geom = P.Geometry(N, datagen.angles_deg(U), K, None, "f64")
+    pl = P.pila_build(geom)
+    img = torch.full((N, N), 0.3, dtype=torch.float64, device="cuda")
+    cost = P.sirt_run(pl, torch.zeros(U, K, dtype=torch.float64, device="cuda"), 0, 0.1, img)
+    assert len(cost) == 0
+    assert torch.all(img == 0.3)

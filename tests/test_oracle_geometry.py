@@ -224,3 +224,50 @@ def test_ray_listing_matches_pila(oracle_lib):
     for g in range(U * K):
         A1[g, pix[off[g]:off[g + 1]]] = rl[off[g]:off[g + 1]]
     assert np.array_equal(A1, _csr_to_dense(N, U, K, (row_ptr, col, ln)))
+
+
+def _exact_chord(N, c, s, sk, i, j):
+    """Chord of the ray x c + y s = sk through pixel (i, j), exact rationals.
+
+    c, s are the double values used by the implementations; the parametric
+    interval is computed exactly and scaled by |(c, s)| at the end.
+    """
+    from fractions import Fraction as F
+    h = F(N, 2)
+    x0, y0 = F(j) - h, h - 1 - F(i)
+    c, s, sk = F(c), F(s), F(sk)
+    px, py, dx, dy = sk * c, sk * s, -s, c
+    ta, tb = (x0 - px) / dx, (x0 + 1 - px) / dx
+    tc, td = (y0 - py) / dy, (y0 + 1 - py) / dy
+    lo = max(min(ta, tb), min(tc, td))
+    hi = min(max(ta, tb), max(tc, td))
+    if hi <= lo:
+        return 0.0
+    return float(hi - lo) * math.sqrt(float(c * c + s * s))
+
+
+@pytest.mark.parametrize("N,K,deg", [(1024, 1449, 0.25), (1024, 1449, 89.75), (1024, 1449, 44.75),
+                                     (512, 725, 0.5), (256, 367, 1.0)])
+def test_lengths_exact_rational_large_grid(oracle_lib, N, K, deg):
+    """Near-axis rays on large grids: lengths within 1e-13 of exact arithmetic."""
+    cs = oracle_lib.trig([deg])[0]
+    rng = np.random.default_rng(int(deg * 100) + N)
+    worst = 0.0
+    for k in rng.choice(K, size=6, replace=False):
+        pix, ln = oracle_lib.trace_ray(N, K, deg, int(k))
+        for q in rng.choice(len(pix), size=min(40, len(pix)), replace=False) if len(pix) else []:
+            p = int(pix[q])
+            ex = _exact_chord(N, cs[0], cs[1], k - (K - 1) / 2.0, p // N, p % N)
+            worst = max(worst, abs(ex - ln[q]))
+    assert worst <= 1e-13
+
+
+def test_pixel_row_matches_full_pila(oracle_lib):
+    N, U, K = 24, 30, 35
+    ang = datagen.angles_deg(U)
+    mask = datagen.circle_mask(N)
+    row_ptr, col, ln = oracle_lib.pila(N, U, K, ang, mask)
+    for p in range(0, N * N, 7):
+        g, l = oracle_lib.pixel_row(N, U, K, ang, p, mask)
+        assert np.array_equal(g, col[row_ptr[p]:row_ptr[p + 1]])
+        assert np.array_equal(l, ln[row_ptr[p]:row_ptr[p + 1]])
