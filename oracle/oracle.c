@@ -172,8 +172,11 @@ static int siddon_ray(int N, double c_, double sn_, double s_, const uint8_t* ma
         }
         return n;
     }
-    /* point on the ray: (s c - t sn, s sn + t c) */
-    const long double x0 = s * c, y0 = s * sn;
+    /* The ray is the line x c + y sn = s for the given (c, sn), whose norm
+     * rho differs from 1 by rounding: its foot point is s (c, sn) / rho^2,
+     * and (-sn, c) has length rho, so parameter differences scale by rho. */
+    const long double rho2 = c * c + sn * sn, rho = sqrtl(rho2);
+    const long double x0 = s * c / rho2, y0 = s * sn / rho2;
     long double tx1 = (x0 + h) / sn, tx2 = (x0 - h) / sn;
     long double ty1 = (-h - y0) / c, ty2 = (h - y0) / c;
     long double tlo = fmaxl(fminl(tx1, tx2), fminl(ty1, ty2));
@@ -193,7 +196,7 @@ static int siddon_ray(int N, double c_, double sn_, double s_, const uint8_t* ma
     qsort(ts, (size_t)nt, sizeof(long double), cmp_ld);
     int last = -1;
     for (int q = 0; q + 1 < nt; ++q) {
-        long double d = ts[q + 1] - ts[q];
+        long double d = (ts[q + 1] - ts[q]) * rho;
         if (!(d > 0.0L)) continue;
         long double tm = 0.5L * (ts[q] + ts[q + 1]);
         long j = col_of(x0 - tm * sn, h);

@@ -116,14 +116,17 @@ __device__ __forceinline__ double sum_err(double a, double b, double s)
     return (a - (s - bb)) + (b - bb);
 }
 
-// t = sk - (xc c + yc s), accurate to a few ulp of t
-__device__ __forceinline__ double ray_offset(double sk, double xc, double yc, double c, double s)
+// t = sk - (xc c + yc s) as an unevaluated sum hi + *lo (error-free
+// products and sums: the pair is exact to about 1e-32)
+__device__ __forceinline__ double ray_offset(double sk, double xc, double yc, double c, double s,
+                                             double* lo)
 {
     const double p = xc * c, ep = fma(xc, c, -p);
     const double q = yc * s, eq = fma(yc, s, -q);
     const double a = sk - p, ea = sum_err(sk, -p, a);
     const double b = a - q, eb = sum_err(a, -q, b);
-    return b + ((ea + eb) - (ep + eq));
+    *lo = (ea + eb) - (ep + eq);
+    return b;
 }
 
 __device__ __forceinline__ double pixel_ray_length(double xl, double yb, double c, double s,
@@ -137,15 +140,24 @@ __device__ __forceinline__ double pixel_ray_length(double xl, double yb, double 
         const double y = sk * s;
         return (y >= yb && y < yb + 1.0) ? 1.0 : 0.0;
     }
-    const double t = fabs(ray_offset(sk, xl + 0.5, yb + 0.5, c, s));
+    double th_lo;
+    const double th = ray_offset(sk, xl + 0.5, yb + 0.5, c, s, &th_lo);
+    const double t = fabs(th + th_lo);
     const double a = fabs(c), b = fabs(s);
     const double hi = fmax(a, b), lo = fmin(a, b);
     const double flat = 0.5 * (hi - lo), edge = 0.5 * (hi + lo);
     double l = 0.0;
-    if (t <= flat)
+    if (t <= flat) {
         l = 1.0 / hi;
-    else if (t < edge)
-        l = (edge - t) / (hi * lo);
+    } else if (t < edge) {
+        // 2 (edge - |t|) = (E - 2|th|) + (E_err - 2 sgn th_lo) with E = hi + lo
+        // split error-free; on the ramp the first difference is exact
+        // (Sterbenz) whenever the slope 1 / (hi lo) is large
+        const double sg = th < 0.0 ? -1.0 : 1.0;
+        const double E = hi + lo, Ee = sum_err(hi, lo, E);
+        const double u = 0.5 * ((E - 2.0 * sg * th) + (Ee - 2.0 * sg * th_lo));
+        l = u / (hi * lo);
+    }
     return l > kTau ? l : 0.0;
 }
 

@@ -36,8 +36,9 @@ def dense_system(N: int, U: int, K: int, angles, mask=None) -> np.ndarray:
         c, s = trig(float(deg))
         for k in range(K):
             g = u * K + k
-            px, py = sk[k] * c, sk[k] * s      # point on the ray
-            dx, dy = -s, c                     # unit direction
+            rho2 = c * c + s * s               # 1 up to rounding
+            px, py = sk[k] * c / rho2, sk[k] * s / rho2   # foot point on x c + y s = sk
+            dx, dy = -s, c                     # direction, length sqrt(rho2)
             if dx == 0.0:                      # vertical ray, half-open columns
                 A[g] = ((px >= x0) & (px < x0 + 1.0)).astype(np.float64)
             elif dy == 0.0:                    # horizontal ray, half-open rows
@@ -49,7 +50,7 @@ def dense_system(N: int, U: int, K: int, angles, mask=None) -> np.ndarray:
                 td = (y0 + 1.0 - py) / dy
                 tlo = np.maximum(np.minimum(ta, tb), np.minimum(tc, td))
                 thi = np.minimum(np.maximum(ta, tb), np.maximum(tc, td))
-                A[g] = np.maximum(thi - tlo, 0.0)
+                A[g] = np.maximum(thi - tlo, 0.0) * math.sqrt(rho2)
     A[A <= TAU] = 0.0
     if mask is not None:
         A[:, np.asarray(mask).reshape(-1) == 0] = 0.0
@@ -63,7 +64,8 @@ def slab_length(N: int, c: float, s: float, sk: float) -> float:
     (left / bottom) side, as the half-open pixel rule gives it.
     """
     h = N / 2.0
-    px, py, dx, dy = sk * c, sk * s, -s, c
+    rho2 = c * c + s * s
+    px, py, dx, dy = sk * c / rho2, sk * s / rho2, -s, c
     lo, hi = -math.inf, math.inf
     for p, d in ((px, dx), (py, dy)):
         if d == 0.0:
@@ -73,4 +75,4 @@ def slab_length(N: int, c: float, s: float, sk: float) -> float:
         t1, t2 = (-h - p) / d, (h - p) / d
         lo = max(lo, min(t1, t2))
         hi = min(hi, max(t1, t2))
-    return max(hi - lo, 0.0)
+    return max(hi - lo, 0.0) * math.sqrt(rho2)

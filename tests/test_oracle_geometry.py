@@ -227,27 +227,31 @@ def test_ray_listing_matches_pila(oracle_lib):
 
 
 def _exact_chord(N, c, s, sk, i, j):
-    """Chord of the ray x c + y s = sk through pixel (i, j), exact rationals.
+    """Chord of the line x c + y s = sk through pixel (i, j), exact rationals.
 
-    c, s are the double values used by the implementations; the parametric
-    interval is computed exactly and scaled by |(c, s)| at the end.
+    c, s are the double values used by the implementations (so c^2 + s^2 is
+    1 only up to rounding); the foot point sk (c, s) / (c^2 + s^2) lies
+    exactly on the line, the parametric interval is exact, and it is scaled
+    by |(c, s)| at the end.
     """
     from fractions import Fraction as F
     h = F(N, 2)
     x0, y0 = F(j) - h, h - 1 - F(i)
     c, s, sk = F(c), F(s), F(sk)
-    px, py, dx, dy = sk * c, sk * s, -s, c
+    rho2 = c * c + s * s
+    px, py, dx, dy = sk * c / rho2, sk * s / rho2, -s, c
     ta, tb = (x0 - px) / dx, (x0 + 1 - px) / dx
     tc, td = (y0 - py) / dy, (y0 + 1 - py) / dy
     lo = max(min(ta, tb), min(tc, td))
     hi = min(max(ta, tb), max(tc, td))
     if hi <= lo:
         return 0.0
-    return float(hi - lo) * math.sqrt(float(c * c + s * s))
+    return float(hi - lo) * math.sqrt(float(rho2))
 
 
 @pytest.mark.parametrize("N,K,deg", [(1024, 1449, 0.25), (1024, 1449, 89.75), (1024, 1449, 44.75),
-                                     (512, 725, 0.5), (256, 367, 1.0)])
+                                     (1024, 1449, 92.25), (1024, 1449, 1.0), (512, 725, 0.5),
+                                     (256, 367, 1.0), (10, 15, 1e-3)])
 def test_lengths_exact_rational_large_grid(oracle_lib, N, K, deg):
     """Near-axis rays on large grids: lengths within 1e-13 of exact arithmetic."""
     cs = oracle_lib.trig([deg])[0]
