@@ -79,7 +79,7 @@ typedef struct pila_geom {
 typedef struct pila_csr {
     int64_t nnz;       /* out of phase 1 */
     int32_t n_support; /* out of phase 1 */
-    int32_t reserved;
+    int32_t max_row;   /* out of phase 1: longest pixel-major row (entries) */
     int64_t* row_ptr;
     int32_t* col;
     void* len;
@@ -96,8 +96,9 @@ typedef struct pila_csr {
  * angle, Eq. 5), stored pixel-major and ray-major.
  *
  * Two phases.  Phase 1 (csr->col == NULL): needs csr->row_ptr, csr->trig
- * and csr->t_row_ptr; fills them, sets csr->nnz and csr->n_support, and
- * synchronises the stream.  Phase 2 (csr->col != NULL): needs every array,
+ * and csr->t_row_ptr; fills them, sets csr->nnz, csr->n_support and
+ * csr->max_row, and synchronises the stream.  pila_build allocates and
+ * frees a temporary device buffer of N*N + 256 bytes during each phase.  Phase 2 (csr->col != NULL): needs every array,
  * sized from phase 1; row_ptr/t_row_ptr must still hold phase 1's output.
  * Fills col, len, support, t_col, t_len and synchronises.
  * Errors: EINVAL for n, U or K < 1, a non-finite angle, a NULL array, or

@@ -38,7 +38,7 @@ class CGeom(C.Structure):
 
 
 class CCsr(C.Structure):
-    _fields_ = [("nnz", C.c_int64), ("n_support", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("nnz", C.c_int64), ("n_support", C.c_int32), ("max_row", C.c_int32),
                 ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("len", C.c_void_p),
                 ("support", C.c_void_p), ("trig", C.c_void_p), ("t_row_ptr", C.c_void_p),
                 ("t_col", C.c_void_p), ("t_len", C.c_void_p)]
@@ -168,13 +168,14 @@ class Geometry:
 class Pila:
     """A built PILA: device tensors plus the C descriptor pointing at them."""
 
-    def __init__(self, geom: Geometry, tensors: dict, nnz: int, n_support: int):
+    def __init__(self, geom: Geometry, tensors: dict, nnz: int, n_support: int, max_row: int):
         self.geom = geom
         self.t = tensors
         self.nnz = nnz
         self.n_support = n_support
+        self.max_row = max_row
         t = tensors
-        self._c = CCsr(nnz, n_support, 0, _ptr(t["row_ptr"]), _ptr(t["col"]), _ptr(t["len"]),
+        self._c = CCsr(nnz, n_support, max_row, _ptr(t["row_ptr"]), _ptr(t["col"]), _ptr(t["len"]),
                        _ptr(t["support"]), _ptr(t["trig"]), _ptr(t["t_row_ptr"]), _ptr(t["t_col"]),
                        _ptr(t["t_len"]))
 
@@ -201,7 +202,7 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     csr = CCsr(0, 0, 0, row_ptr.data_ptr(), None, None, None, trig.data_ptr(), t_row_ptr.data_ptr(),
                None, None)
     _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
-    nnz, P = int(csr.nnz), int(csr.n_support)
+    nnz, P, max_row = int(csr.nnz), int(csr.n_support), int(csr.max_row)
     ldt = torch.float64 if geom.len_dtype == PILA_F64 else torch.float32
     col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
     ln = torch.empty(max(nnz, 1), dtype=ldt, device=dev)
@@ -214,7 +215,7 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
     return Pila(geom, dict(row_ptr=row_ptr, col=col[:nnz], len=ln[:nnz], support=support[:P],
                            trig=trig, t_row_ptr=t_row_ptr, t_col=t_col[:nnz], t_len=t_ln[:nnz]),
-                nnz, P)
+                nnz, P, max_row)
 
 
 def pila_forward(pila: Pila, image, out=None):

@@ -150,6 +150,27 @@ __global__ __launch_bounds__(256) void ray_rows_kernel(int32_t N, int32_t U, int
     if (!FILL && lane == 0) t_row_ptr[g + 1] = total;
 }
 
+// out[0] = max of a[1..n) (the row counts before the scan), one workgroup
+__global__ __launch_bounds__(1024) void max_count_kernel(const int64_t* __restrict__ a, int64_t n,
+                                                         int64_t* __restrict__ out)
+{
+    __shared__ int64_t wmax[16];
+    int64_t m = 0;
+    for (int64_t q = 1 + threadIdx.x; q < n; q += 1024) m = a[q] > m ? a[q] : m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t r = 0;
+        for (int w = 0; w < 16; ++w) r = wmax[w] > r ? wmax[w] : r;
+        out[0] = r;
+    }
+}
+
 // In-place inclusive scan of a[0..n) by one workgroup of 1024 threads.
 // a[0] is 0 and a[x+1] holds the count of row x, so the result is the CSR
 // offset array.
@@ -240,12 +261,15 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
     for (int64_t p = 0; p < NP; ++p)
         if (!geom->mask || geom->mask[p]) support.push_back((int32_t)p);
 
-    DeviceBuffer dmask;
+    // temporary device buffer: [0, 256) small results, [256, 256 + N*N) the mask
+    DeviceBuffer tmp;
+    PILA_HIP(hipMalloc(&tmp.p, 256 + (size_t)NP));
+    int64_t* d_small = (int64_t*)tmp.p;
+    const uint8_t* mk = nullptr;
     if (geom->mask) {
-        PILA_HIP(hipMalloc(&dmask.p, (size_t)NP));
-        PILA_HIP(hipMemcpyAsync(dmask.p, geom->mask, (size_t)NP, hipMemcpyHostToDevice, st));
+        PILA_HIP(hipMemcpyAsync((char*)tmp.p + 256, geom->mask, (size_t)NP, hipMemcpyHostToDevice, st));
+        mk = (const uint8_t*)tmp.p + 256;
     }
-    const uint8_t* mk = (const uint8_t*)dmask.p;
 
     if (!csr->col) {  // phase 1: trig, offsets, sizes
         std::vector<double> cs(2 * (size_t)U);
@@ -257,21 +281,24 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
         pixel_rows_kernel<false, double><<<blocks_for(NP), 256, 0, st>>>(
             N, U, K, csr->trig, mk, csr->row_ptr, nullptr, nullptr);
         PILA_HIP(hipGetLastError());
+        max_count_kernel<<<1, 1024, 0, st>>>(csr->row_ptr, NP + 1, d_small);
         scan_kernel<<<1, 1024, 0, st>>>(csr->row_ptr, NP + 1);
         ray_rows_kernel<false, double><<<blocks_for(G), 256, 0, st>>>(N, U, K, csr->trig, mk,
                                                                      csr->t_row_ptr, nullptr, nullptr);
         PILA_HIP(hipGetLastError());
         scan_kernel<<<1, 1024, 0, st>>>(csr->t_row_ptr, G + 1);
         PILA_HIP(hipGetLastError());
-        int64_t tot[2] = {0, 0};
+        int64_t tot[3] = {0, 0, 0};
         PILA_HIP(hipMemcpyAsync(&tot[0], csr->row_ptr + NP, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         PILA_HIP(hipMemcpyAsync(&tot[1], csr->t_row_ptr + G, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        PILA_HIP(hipMemcpyAsync(&tot[2], d_small, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         PILA_HIP(hipStreamSynchronize(st));
         if (tot[0] != tot[1])
             return fail(PILA_EHIP, "pixel-major (%lld) and ray-major (%lld) entry counts differ",
                         (long long)tot[0], (long long)tot[1]);
         csr->nnz = tot[0];
         csr->n_support = (int32_t)support.size();
+        csr->max_row = (int32_t)tot[2];
         return PILA_OK;
     }
 

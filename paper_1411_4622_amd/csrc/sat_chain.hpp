@@ -1,0 +1,831 @@
+// Device side of the simulated annealing chains (section II-A Steps 1-4,
+// section II-B Eq. 6-7, section III Eq. 8, section III-B BoME).
+//
+// One workgroup runs one chain; the host is not involved between steps.  Per
+// step every estimate's change of the squared-residual sum,
+// S_m = sum over its PILA row of l d (2 r + l d) (Eq. 7's inner sum), is
+// reduced by the lanes that own it; after a barrier every wavefront takes the
+// same first minimum over the M sums (BoME) and the same Metropolis decision
+// on Delta C = sqrt(C^2 + S/KU) - C, written cancellation-free; the owner of
+// an accepted estimate applies Eq. 6 to the residual (a row's rays are
+// distinct, so no atomics) and a second barrier publishes it.
+//
+// Two bodies share this logic and give bit-identical results:
+//  * run_chain_piped: the estimates do not depend on the chain state, so
+//    Philox draws, support lookups and row offsets are computed a block of
+//    steps at a time (one lane per step and estimate) and each estimate's row
+//    is loaded into registers two steps ahead.  The image value and (when the
+//    residual lives in global memory) the residual values are loaded one step
+//    ahead and patched with the previous step's accepted change: the owner
+//    publishes the new residual values of its row in a small LDS table keyed
+//    by (angle, bin parity) and tagged with the step.  Rows must fit the
+//    registers (max_row <= LPC * E).
+//  * run_chain_simple: any row length and any M.
+//
+// Canonical sums: a row sum S is the sum of 64 partials (partial j takes the
+// entries q = j mod 64 in ascending q, fused multiply-add) combined by an
+// xor butterfly with distances 1, 2, 4, 8, 16, 32.  A workgroup of any shape
+// with 16, 32 or 64 lanes per estimate forms exactly these operations (lanes
+// keep 64 / LPC partials), so the result does not depend on the launch shape.
+// Residual rebuilds use one wavefront per ray with the same 64-partial sum,
+// 64-ray tiles summed by the same butterfly, and tiles summed lane-strided.
+//
+// Visibility: within a workgroup (all waves on one CU, one vector L1) a
+// store issued before s_barrier is seen by loads other waves issue after it,
+// so barriers only drain LDS traffic and prefetched global loads stay in
+// flight across them.
+#pragma once
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace pila {
+
+// Chain state carried between launches of a segmented chain.
+struct ChainCarry {
+    int64_t s_next, accepts, accepts_nz, since;
+    int32_t resyncs, status, resync_due, done;
+    double sse, T0, TN, drift_r, drift_sse;
+};
+
+struct ChainJob {
+    int32_t N, U, K, P;
+    int32_t precision, m_cand, n_stages, q_auto;
+    int32_t max_row, pad;
+    int64_t n_steps, resync_every;
+    uint64_t seed, chain_id;
+    double T0, TN, tn_ratio, delta_max, f_min, f_max, ln09;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const void* len;
+    const int64_t* t_row_ptr;
+    const int32_t* t_col;
+    const void* t_len;
+    const int32_t* support;
+    const double* sino;
+    double* f;
+    void* r;          // residual, U*K values of the chain's precision (global mode)
+    double* tsum;     // per 64-ray tile: sum of squared residuals (ceil(U*K/64))
+    double* tdrift;   // per tile: max |r_old - r64| at a rebuild
+    ChainCarry* carry;
+    sat_stats* stats;
+    int32_t* tr_m;
+    uint8_t* tr_acc;
+    double* tr_dc;
+};
+
+constexpr int kMaxCand = 64;
+constexpr int kMaxWaves = 16;
+
+struct ChainShared {
+    double S[kMaxCand];
+    double fn[kMaxCand];
+    double d[kMaxCand];
+    int32_t p[kMaxCand];
+    double red[kMaxWaves];
+    double scalar[4];
+    double fnstar;
+    int32_t pstar;
+    int32_t ticket;
+};
+
+// pipelined workgroups hold at most 8 wavefronts (up to 256 registers per lane)
+constexpr int kPipedThreads = 512;
+
+// ---------------------------------------------------------------------------
+// lane primitives
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swz16(float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+}
+__device__ __forceinline__ double swz16(double x)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+
+// value of lane ^ O (O = 1, 2, 4, 8, 16, 32).  For O = 4 and O = 8 the row
+// mirrors are used, which equal the xor partner once every quad (O = 4) or
+// half-row (O = 8) holds one value, as it does inside a butterfly.
+template <int O, typename T>
+__device__ __forceinline__ T xor_partner(T x)
+{
+    if constexpr (O == 1) return dpp_mov<0xB1>(x);
+    else if constexpr (O == 2) return dpp_mov<0x4E>(x);
+    else if constexpr (O == 4) return dpp_mov<0x141>(x);
+    else if constexpr (O == 8) return dpp_mov<0x140>(x);
+    else if constexpr (O == 16) return swz16(x);
+    else return __shfl_xor(x, 32, kWave);
+}
+
+template <int O, int LPC, int K, typename T>
+__device__ __forceinline__ void butterfly_level(T (&a)[K])
+{
+    if constexpr (O < LPC) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[k] = a[k] + xor_partner<O>(a[k]);
+    } else {
+        constexpr int st = O / LPC;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (!(k & st)) {
+                const T t = a[k] + a[k ^ st];
+                a[k] = t;
+                a[k ^ st] = t;
+            }
+    }
+}
+
+// Canonical 64-partial sum for groups of LPC lanes holding K = 64 / LPC
+// partials each (partial j = lane-in-group + k * LPC); every lane of the
+// group returns the total.
+template <int LPC, typename T>
+__device__ __forceinline__ T canon_sum(T (&a)[64 / LPC])
+{
+    constexpr int K = 64 / LPC;
+    butterfly_level<1, LPC, K>(a);
+    butterfly_level<2, LPC, K>(a);
+    butterfly_level<4, LPC, K>(a);
+    butterfly_level<8, LPC, K>(a);
+    butterfly_level<16, LPC, K>(a);
+    butterfly_level<32, LPC, K>(a);
+    return a[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_canon_sum(T x)
+{
+    T a[1] = {x};
+    return canon_sum<64>(a);
+}
+
+__device__ __forceinline__ double wave_min(double x)
+{
+    x = fmin(x, xor_partner<1>(x));
+    x = fmin(x, xor_partner<2>(x));
+    x = fmin(x, xor_partner<4>(x));
+    x = fmin(x, xor_partner<8>(x));
+    x = fmin(x, xor_partner<16>(x));
+    x = fmin(x, xor_partner<32>(x));
+    return x;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---------------------------------------------------------------------------
+// schedule (Eq. 2): stage n = floor(s n_stages / n_steps), tracked
+// incrementally without a 64-bit division per step
+// ---------------------------------------------------------------------------
+struct Schedule {
+    int64_t stage, next;  // current stage, first step of the following stage
+    double T0, dT;
+    __device__ void start(int64_t s, int64_t n_steps, int32_t n_stages, double t0, double tn)
+    {
+        T0 = t0;
+        dT = (t0 - tn) / (double)n_stages;
+        stage = n_steps > 0 ? (s * (int64_t)n_stages) / n_steps : 0;
+        next = first_of(stage + 1, n_steps, n_stages);
+    }
+    __device__ static int64_t first_of(int64_t k, int64_t n_steps, int32_t n_stages)
+    {
+        return (k * n_steps + n_stages - 1) / n_stages;
+    }
+    __device__ double at(int64_t s, int64_t n_steps, int32_t n_stages)
+    {
+        while (s >= next) {
+            ++stage;
+            next = first_of(stage + 1, n_steps, n_stages);
+        }
+        return T0 - (double)stage * dT;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// estimates, rebuilds and ordered sums
+// ---------------------------------------------------------------------------
+
+// Draw one estimate (Step 2, Eq. 3 with a clamp to [f_min, f_max]) and return
+// its row sum (whole wavefront, canonical order) in every lane.
+template <typename Real>
+__device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint64_t c0, uint64_t c1,
+                             uint64_t c2, int lane, int32_t* p_out, double* fn_out, double* d_out)
+{
+    const Words4 w = philox4x64(J.seed, J.chain_id, c0, c1, c2, 0);
+    const int32_t p = J.support[__umul64hi(w.w0, (uint64_t)J.P)];
+    const double delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+    const double fo = J.f[p];
+    double fn = fo + delta;
+    if (fn < J.f_min) fn = J.f_min;
+    if (fn > J.f_max) fn = J.f_max;
+    const double d = fn - fo;
+    const Real* len = (const Real*)J.len;
+    const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
+    const Real dr = (Real)d;
+    Real acc = 0;
+    for (int64_t q = b + lane; q < e; q += kWave) {
+        const Real t = dr * len[q];
+        acc = fma(t, (Real)2 * r[J.col[q]] + t, acc);
+    }
+    *p_out = p;
+    *fn_out = fn;
+    *d_out = d;
+    return wave_canon_sum(acc);
+}
+
+// One 64-ray tile of a from-scratch FP64 residual r = A f - Pm (Eq. 1,
+// Eq. 4): ray t*64 + j ends in lane j.  Writes r (chain precision), the
+// tile's sum of squares and (if measure) its max |r_old - r64|.
+template <typename Real>
+__device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int t, bool measure,
+                             int lane)
+{
+    const Real* tl = (const Real*)J.t_len;
+    double mine = 0.0;
+    for (int k = 0; k < kWave; ++k) {
+        const int g = t * kWave + k;
+        if (g >= G) break;
+        const int64_t b = J.t_row_ptr[g], e = J.t_row_ptr[g + 1];
+        double acc = 0.0;
+        for (int64_t q = b + lane; q < e; q += kWave) acc = fma((double)tl[q], J.f[J.t_col[q]], acc);
+        acc = wave_canon_sum(acc);
+        if (lane == k) mine = acc;
+    }
+    const int g = t * kWave + lane;
+    double sq = 0.0, dr = 0.0;
+    if (g < G) {
+        const double r64 = mine - J.sino[g];
+        if (measure) dr = fabs((double)r[g] - r64);
+        r[g] = (Real)r64;
+        sq = r64 * r64;
+    }
+    sq = wave_canon_sum(sq);
+    if (measure) dr = wave_min(-dr) * -1.0;  // max over the tile
+    if (lane == 0) {
+        J.tsum[t] = sq;
+        if (measure) J.tdrift[t] = dr;
+    }
+}
+
+// sum of the tile sums (lane-strided, then the butterfly) and max of the tile
+// drifts, by one wavefront; every lane gets the results
+__device__ inline void tile_totals(const ChainJob& J, int G, bool measure, int lane, double* sse,
+                                   double* drift)
+{
+    const int T = (G + kWave - 1) / kWave;
+    double a = 0.0, m = 0.0;
+    for (int t = lane; t < T; t += kWave) {
+        a += J.tsum[t];
+        if (measure) m = fmax(m, J.tdrift[t]);
+    }
+    *sse = wave_canon_sum(a);
+    *drift = measure ? -wave_min(-m) : 0.0;
+}
+
+// in-workgroup rebuild of the whole residual; returns (sse, drift) to all
+template <typename Real>
+__device__ void rebuild_in_group(const ChainJob& J, Real* r, ChainShared& sh, bool measure, int lane,
+                                 int wave, int NW, double* sse, double* drift)
+{
+    const int G = J.U * J.K;
+    const int T = (G + kWave - 1) / kWave;
+    __syncthreads();
+    for (int t = wave; t < T; t += NW) rebuild_tile<Real>(J, r, G, t, measure, lane);
+    __syncthreads();
+    if (wave == 0) {
+        double s, d;
+        tile_totals(J, G, measure, lane, &s, &d);
+        if (lane == 0) {
+            sh.scalar[0] = s;
+            sh.scalar[1] = d;
+        }
+    }
+    __syncthreads();
+    *sse = uniform_f64(sh.scalar[0]);
+    *drift = uniform_f64(sh.scalar[1]);
+    __syncthreads();
+}
+
+struct ChainState {
+    double sse, T0, TN, drift_r, drift_sse;
+    int64_t n_steps, accepts, accepts_nz, since, s_begin;
+    int32_t status, resyncs;
+};
+
+// Eq. 8: T0 from q_auto uphill single-pixel estimates of the starting image
+// (Philox counter (q, 0, 2, 0)), summed in q order.
+template <typename Real>
+__device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, ChainShared& sh, int lane,
+                                 int wave, int NW, double* T0, double* TN, int32_t* status)
+{
+    const double KU = (double)J.K * (double)J.U;
+    const int64_t limit = 1000 * (int64_t)J.q_auto;
+    int64_t found = 0;
+    double sum = 0.0;
+    for (int64_t q0 = 0; q0 < limit && found < J.q_auto; q0 += NW) {
+        const int64_t q = q0 + wave;
+        if (q < limit) {
+            int32_t p;
+            double fn, d;
+            const double S = (double)estimate_sum<Real>(J, r, (uint64_t)q, 0, 2, lane, &p, &fn, &d);
+            const double cn = sqrt(fmax(sse + S, 0.0) / KU), co = sqrt(sse / KU);
+            const double den = cn + co;
+            if (lane == 0) sh.S[wave] = den == 0.0 ? 0.0 : (S / KU) / den;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < NW && q0 + w < limit && found < J.q_auto; ++w) {
+                const double dC = sh.S[w];
+                if (dC > 0.0) {
+                    sum += dC;
+                    ++found;
+                }
+            }
+            sh.scalar[2] = sum;
+            sh.scalar[3] = (double)found;
+        }
+        __syncthreads();
+        sum = uniform_f64(sh.scalar[2]);
+        found = (int64_t)uniform_f64(sh.scalar[3]);
+        __syncthreads();
+    }
+    if (found < J.q_auto) {
+        *status = PILA_EINVAL;
+        *T0 = *TN = 0.0;
+    } else {
+        *status = PILA_OK;
+        *T0 = -sum / ((double)J.q_auto * J.ln09);
+        *TN = *T0 / J.tn_ratio;
+    }
+}
+
+// Step 1 and Eq. 8 inside the workgroup.
+template <typename Real>
+__device__ ChainState chain_setup(const ChainJob& J, Real* r, ChainShared& sh, int lane, int wave, int NW)
+{
+    ChainState cs;
+    double drift;
+    rebuild_in_group<Real>(J, r, sh, false, lane, wave, NW, &cs.sse, &drift);
+    cs.T0 = J.T0;
+    cs.TN = J.TN;
+    cs.status = PILA_OK;
+    if (!(cs.T0 > 0.0)) auto_temperature<Real>(J, r, cs.sse, sh, lane, wave, NW, &cs.T0, &cs.TN, &cs.status);
+    cs.n_steps = cs.status == PILA_OK ? J.n_steps : 0;
+    cs.accepts = cs.accepts_nz = cs.since = cs.s_begin = 0;
+    cs.resyncs = 0;
+    cs.drift_r = cs.drift_sse = 0.0;
+    return cs;
+}
+
+__device__ inline ChainState load_carry(const ChainJob& J)
+{
+    const ChainCarry& c = *J.carry;
+    ChainState cs;
+    cs.sse = c.sse;
+    cs.T0 = c.T0;
+    cs.TN = c.TN;
+    cs.drift_r = c.drift_r;
+    cs.drift_sse = c.drift_sse;
+    cs.status = c.status;
+    cs.n_steps = c.status == PILA_OK ? J.n_steps : 0;
+    cs.accepts = c.accepts;
+    cs.accepts_nz = c.accepts_nz;
+    cs.since = c.since;
+    cs.s_begin = c.s_next;
+    cs.resyncs = c.resyncs;
+    return cs;
+}
+
+__device__ inline void save_carry(const ChainJob& J, const ChainState& cs, int64_t s_next, bool resync_due)
+{
+    if (threadIdx.x != 0) return;
+    ChainCarry& c = *J.carry;
+    c.s_next = s_next;
+    c.accepts = cs.accepts;
+    c.accepts_nz = cs.accepts_nz;
+    c.since = cs.since;
+    c.resyncs = cs.resyncs;
+    c.status = cs.status;
+    c.resync_due = resync_due ? 1 : 0;
+    c.done = s_next >= cs.n_steps ? 1 : 0;
+    c.sse = cs.sse;
+    c.T0 = cs.T0;
+    c.TN = cs.TN;
+    c.drift_r = cs.drift_r;
+    c.drift_sse = cs.drift_sse;
+}
+
+__device__ inline void write_stats(const ChainJob& J, const ChainState& cs)
+{
+    if (threadIdx.x == 0 && J.stats) {
+        const double KU = (double)J.K * (double)J.U;
+        sat_stats st;
+        st.steps = cs.n_steps;
+        st.accepts = cs.accepts;
+        st.accepts_nonzero = cs.accepts_nz;
+        st.resyncs = cs.resyncs;
+        st.status = cs.status;
+        st.T0_used = cs.T0;
+        st.TN_used = cs.TN;
+        st.sse_final = cs.sse;
+        st.cost_final = sqrt(fmax(cs.sse, 0.0) / KU);
+        st.max_drift_r = cs.drift_r;
+        st.max_drift_sse = cs.drift_sse;
+        *J.stats = st;
+    }
+    __syncthreads();
+}
+
+struct Decision {
+    int ms;
+    double S, dC;
+    bool accept;
+};
+
+// BoME (first minimal S; a NaN never wins) and Step 4's acceptance.  Every
+// wavefront computes the same answer; each lane forms the cost change of its
+// own estimate so the cost arithmetic overlaps the minimum search.
+__device__ __forceinline__ Decision decide(const double* S, int M, int lane, double sse, double co,
+                                           double KU, double T, double N1)
+{
+    double v = lane < M ? S[lane] : INFINITY;
+    if (v != v) v = INFINITY;
+    const double cn = sqrt(fmax(sse + v, 0.0) / KU);
+    const double den = cn + co;
+    const double dC = den == 0.0 ? 0.0 : (v / KU) / den;
+    const double ex = exp(-dC / T);
+    const double vmin = wave_min(v);
+    const unsigned long long mask = __ballot(v == vmin);
+    Decision dn;
+    dn.ms = mask ? uniform_i32(__ffsll((long long)mask) - 1) : 0;
+    dn.S = readlane_f64(v, dn.ms);
+    dn.dC = readlane_f64(dC, dn.ms);
+    const double ex_s = readlane_f64(ex, dn.ms);
+    dn.accept = (dn.dC <= 0.0) || (N1 < ex_s);
+    return dn;
+}
+
+// bookkeeping and trace after a decision; d_star is the winner's change
+__device__ __forceinline__ void count_decision(const ChainJob& J, ChainState& cs, const Decision& dn,
+                                               double d_star, int64_t s)
+{
+    if (dn.accept) {
+        cs.sse += dn.S;
+        ++cs.accepts;
+        if (d_star != 0.0) {
+            ++cs.accepts_nz;
+            ++cs.since;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (J.tr_m) J.tr_m[s] = dn.ms;
+        if (J.tr_acc) J.tr_acc[s] = dn.accept ? 1 : 0;
+        if (J.tr_dc) J.tr_dc[s] = dn.dC;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void resync_in_group(const ChainJob& J, ChainState& cs, Real* r, ChainShared& sh,
+                                                int lane, int wave, int NW)
+{
+    double sse64, drift;
+    rebuild_in_group<Real>(J, r, sh, true, lane, wave, NW, &sse64, &drift);
+    cs.drift_r = fmax(cs.drift_r, drift);
+    const double ds = sse64 > 0.0 ? fabs(cs.sse - sse64) / sse64 : fabs(cs.sse - sse64);
+    cs.drift_sse = fmax(cs.drift_sse, ds);
+    cs.sse = sse64;
+    cs.since = 0;
+    ++cs.resyncs;
+}
+
+// ---------------------------------------------------------------------------
+// any row length, any M
+// ---------------------------------------------------------------------------
+template <typename Real, bool LDS>
+__device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+    const double KU = (double)J.K * (double)J.U;
+    const int M = J.m_cand;
+    Real* r = LDS ? (Real*)lds : (Real*)J.r;
+    ChainState cs = chain_setup<Real>(J, r, sh, lane, wave, NW);
+    Schedule sched;
+    sched.start(0, cs.n_steps, J.n_stages, cs.T0, cs.TN);
+    const bool f32 = sizeof(Real) == 4;
+
+    for (int64_t s = 0; s < cs.n_steps; ++s) {
+        const double T = sched.at(s, cs.n_steps, J.n_stages);
+        for (int m = wave; m < M; m += NW) {
+            int32_t p;
+            double fn, d;
+            const Real S = estimate_sum<Real>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
+            if (lane == 0) {
+                sh.S[m] = (double)S;
+                sh.p[m] = p;
+                sh.fn[m] = fn;
+                sh.d[m] = d;
+            }
+        }
+        const double co = sqrt(cs.sse / KU);
+        const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+        __syncthreads();
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, N1);
+        const double d_star = uniform_f64(sh.d[dn.ms]);
+        if (dn.accept && wave == dn.ms % NW) {  // the owner of the winner applies Eq. 6
+            const int32_t p = sh.p[dn.ms];
+            const Real* len = (const Real*)J.len;
+            const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
+            const Real dr = (Real)d_star;
+            for (int64_t q = b + lane; q < e; q += kWave) {
+                const int32_t g = J.col[q];
+                r[g] = r[g] + dr * len[q];
+            }
+            if (lane == 0) J.f[p] = sh.fn[dn.ms];
+        }
+        count_decision(J, cs, dn, d_star, s);
+        if (f32 && J.resync_every > 0 && cs.since >= J.resync_every)
+            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+        __syncthreads();
+    }
+    write_stats(J, cs);
+}
+
+// ---------------------------------------------------------------------------
+// pipelined: rows in registers two steps ahead, operands one step ahead
+// ---------------------------------------------------------------------------
+template <typename Real, int E>
+struct RowSet {
+    int32_t col[E];
+    Real len[E];
+    int32_t tk[E];  // global-residual mode: (2 u + k % 2) << 13 | k of each ray
+    int32_t p, n;   // pixel, row length
+    double delta;   // proposed change before the clamp
+    double N1;      // acceptance uniform of the step
+};
+
+struct Draws {  // one block of steps: lane j <-> (step j / CPW, estimate slot j % CPW)
+    int64_t base;
+    int64_t b;
+    int32_t p, n;
+    double delta, N1;
+};
+
+template <typename Real, bool RLDS, int CPW, int E>
+__device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
+{
+    constexpr int LPC = kWave / CPW;  // lanes per estimate
+    constexpr int BL = kWave / CPW;   // steps per block of draws
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+    const int slot = lane / LPC, li = lane % LPC;
+    const double KU = (double)J.K * (double)J.U;
+    const int M = J.m_cand;
+    const int m_mine = wave * CPW + slot;
+    const bool active = m_mine < M;
+    const int G = J.U * J.K;
+    Real* r = RLDS ? (Real*)lds : (Real*)J.r;
+    // global-residual mode: table of the last accepted row's new residuals
+    int64_t* pkey = (int64_t*)lds;
+    Real* pval = (Real*)(lds + 16 * (size_t)J.U);
+    const Real* lenp = (const Real*)J.len;
+
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
+    const int64_t n_steps = cs.n_steps;
+    const int64_t s_begin = cs.s_begin;
+    if (!RLDS) {
+        for (int q = threadIdx.x; q < 2 * J.U; q += blockDim.x) pkey[q] = -1;
+    }
+    Schedule sched;
+    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN);
+    const float invK = 1.0f / (float)J.K;
+
+    Draws cur, nxt;
+    auto fill = [&](Draws& D, int64_t base) {
+        D.base = base;
+        const int64_t s = base + lane / CPW;
+        const int m = wave * CPW + lane % CPW;
+        D.p = 0;
+        D.n = 0;
+        D.b = 0;
+        D.delta = 0.0;
+        D.N1 = 0.0;
+        if (s < n_steps) {
+            if (m < M) {
+                const Words4 w = philox4x64(J.seed, J.chain_id, (uint64_t)s, (uint64_t)m, 0, 0);
+                D.p = J.support[__umul64hi(w.w0, (uint64_t)J.P)];
+                D.delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+                D.b = J.row_ptr[D.p];
+                D.n = (int32_t)(J.row_ptr[D.p + 1] - D.b);
+            }
+            if (lane % CPW == 0) D.N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+        }
+    };
+    cur.base = nxt.base = -1;
+
+    auto prefetch = [&](RowSet<Real, E>& S, int64_t t) {
+        if (t >= n_steps) {
+            S.p = 0;
+            S.n = 0;
+            S.delta = 0.0;
+            S.N1 = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                S.col[e] = 0;
+                S.len[e] = (Real)0;
+                S.tk[e] = 0;
+            }
+            return;
+        }
+        const int64_t base = t - t % BL;
+        if (cur.base != base) {
+            if (nxt.base == base)
+                cur = nxt;
+            else
+                fill(cur, base);
+        }
+        const int j = (int)(t - base);
+        if (j == BL / 2 && base + BL < n_steps) fill(nxt, base + BL);  // next block, early
+        const int src = j * CPW + slot;
+        S.p = __shfl(cur.p, src, kWave);
+        S.n = __shfl(cur.n, src, kWave);
+        const int64_t b = __shfl(cur.b, src, kWave);
+        S.delta = __shfl(cur.delta, src, kWave);
+        S.N1 = __shfl(cur.N1, j * CPW, kWave);
+        // loads are unconditional (entries past the row read entry 0) so that
+        // nothing waits for them here; validity is tested where they are used
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int q = li + e * LPC;
+            const int64_t at = q < S.n ? b + q : 0;
+            S.col[e] = J.col[at];
+            S.len[e] = lenp[at];
+        }
+    };
+    // ray -> patch-table slot; needs the row's ray indices to have arrived
+    auto table_slots = [&](RowSet<Real, E>& S) {
+        if (RLDS) return;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int g = S.col[e];
+            int u = (int)((float)g * invK);
+            int k = g - u * J.K;
+            if (k < 0) {
+                --u;
+                k += J.K;
+            } else if (k >= J.K) {
+                ++u;
+                k -= J.K;
+            }
+            S.tk[e] = ((2 * u + (k & 1)) << 13) | k;
+        }
+    };
+
+    RowSet<Real, E> A, B, C;
+    Real rvA[E], rvB[E];
+    double foA = 0.0, foB = 0.0;
+    prefetch(A, s_begin);
+    prefetch(B, s_begin + 1);
+    __syncthreads();  // setup (residual, temperatures, patch table) complete
+    table_slots(A);
+#pragma unroll
+    for (int e = 0; e < E; ++e) rvA[e] = r[A.col[e]];
+    foA = J.f[A.p];
+    bool patch = false;     // apply the table of step s - 1 to rvA
+    int32_t lp = -1;        // last accepted pixel (step s - 1) and its value
+    double lfn = 0.0;
+
+    for (int64_t s = s_begin; s < n_steps; ++s) {
+        const double T = sched.at(s, n_steps, J.n_stages);
+        // operands of this step: patch with the previous step's change
+        if (!RLDS && patch) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int tk = A.tk[e];
+                const int64_t key = pkey[tk >> 13];
+                if (key == (((int64_t)(s - 1)) << 13 | (tk & 8191))) rvA[e] = pval[tk >> 13];
+            }
+        }
+        if (A.p == lp) foA = lfn;
+        double fn = foA + A.delta;
+        if (fn < J.f_min) fn = J.f_min;
+        if (fn > J.f_max) fn = J.f_max;
+        const double d = fn - foA;
+        const Real dr = (Real)d;
+        Real part[CPW];
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) part[k] = (Real)0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const Real t = (li + e * LPC < A.n) ? dr * A.len[e] : (Real)0;
+            part[e % CPW] = fma(t, (Real)2 * rvA[e] + t, part[e % CPW]);
+        }
+        const Real S = canon_sum<LPC>(part);
+        if (active && li == 0) {
+            sh.S[m_mine] = (double)S;
+            sh.d[m_mine] = d;
+        }
+        // next step's operands (issued before the row loads of step s + 2)
+        table_slots(B);
+        if (!RLDS) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) rvB[e] = r[B.col[e]];
+        }
+        foB = J.f[B.p];
+        prefetch(C, s + 2);
+        const double co = sqrt(cs.sse / KU);
+        __syncthreads();
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, A.N1);
+        const double d_star = uniform_f64(sh.d[dn.ms]);
+        if (dn.accept && dn.ms == m_mine) {  // the owner of the winner applies Eq. 6
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (li + e * LPC < A.n) {
+                    const Real rn = rvA[e] + dr * A.len[e];
+                    r[A.col[e]] = rn;
+                    if (!RLDS) {
+                        pkey[A.tk[e] >> 13] = ((int64_t)s << 13) | (A.tk[e] & 8191);
+                        pval[A.tk[e] >> 13] = rn;
+                    }
+                }
+            }
+            if (li == 0) {
+                J.f[A.p] = fn;
+                sh.pstar = A.p;
+                sh.fnstar = fn;
+            }
+        }
+        count_decision(J, cs, dn, d_star, s);
+        bool resynced = false;
+        if (sizeof(Real) == 4 && J.resync_every > 0 && cs.since >= J.resync_every) {
+            if (segmented) {  // the FP64 rebuild runs grid-wide between launches
+                save_carry(J, cs, s + 1, true);
+                return;
+            }
+            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            resynced = true;
+        }
+        __syncthreads();
+        if (dn.accept) {
+            lp = uniform_i32(sh.pstar);
+            lfn = uniform_f64(sh.fnstar);
+        } else {
+            lp = -1;
+        }
+        patch = dn.accept && !resynced;
+        A = B;
+        B = C;
+        foA = foB;
+        if (RLDS || resynced) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) rvA[e] = r[A.col[e]];
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) rvA[e] = rvB[e];
+        }
+        if (resynced) {
+            foA = J.f[A.p];
+            lp = -1;
+        }
+    }
+    if (segmented) {
+        save_carry(J, cs, n_steps, false);
+        return;
+    }
+    write_stats(J, cs);
+}
+
+template <typename Real>
+__device__ void run_chain_simple_dispatch(const ChainJob& J, char* lds, int lds_bytes, ChainShared& sh)
+{
+    if ((int64_t)J.U * J.K * (int64_t)sizeof(Real) <= lds_bytes)
+        run_chain_simple<Real, true>(J, lds, sh);
+    else
+        run_chain_simple<Real, false>(J, lds, sh);
+}
+
+}  // namespace pila

@@ -85,7 +85,7 @@ def test_bad_sat_arguments(P):
     rc = lib.sat_run(C.byref(g.c), C.byref(csr), None, C.byref(prm), None, None, 0, None, None, None)
     assert rc == P._binding.PILA_EINVAL
     fake = 0x1000
-    csr = CCsr(10, 5, 0, fake, fake, fake, fake, fake, fake, fake, fake)
+    csr = CCsr(10, 5, 4, fake, fake, fake, fake, fake, fake, fake, fake)
     for bad in (dict(m_cand=0), dict(m_cand=65), dict(n_stages=0), dict(precision="f32"),
                 dict(T0=None, q_auto=0), dict(T0=1.0, TN=-1.0), dict(delta_max=float("nan")),
                 dict(f_min=1.0, f_max=0.0), dict(n_steps=-1)):
@@ -109,7 +109,7 @@ def test_workspace_sizes(P):
     n = C.c_size_t(0)
     p64 = P.SatParams(n_steps=1, precision="f64").c()
     assert lib.sat_workspace_size(C.byref(g.c), C.byref(p64), C.byref(n)) == 0
-    assert n.value >= 90 * 64 * 16
+    assert n.value >= 90 * 64 * 8
     sp = CSirtParams(10, 0, 0.1)
     assert lib.sirt_workspace_size(C.byref(g.c), C.byref(sp), C.byref(n)) == 0
     assert n.value >= 2 * 90 * 64 * 8

@@ -149,7 +149,7 @@ def test_deterministic_and_launch_independent(P):
     geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
     pl = P.pila_build(geom)
     sino = torch.from_numpy(sl.sino).cuda()
-    for waves in (1, 4, 16):
+    for waves in (1, 2, 4, 8, 16):
         img = torch.from_numpy(sl.f0.copy()).cuda()
         st = P.sat_run_batch([P.Job(pl, sino, img, prm)], waves_per_chain=waves, chains_per_cu=2)
         assert np.array_equal(img.cpu().numpy(), a[0]), waves
