@@ -38,21 +38,35 @@ def log(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int, resyncs: int, nnz: int,
-                G: int) -> float:
-    """Algorithmic bytes one chain launch must move (FP32 PILA and residual).
+def chain_kernel_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
+    """Algorithmic bytes of the chain kernel over a whole chain (FP32 PILA and residual).
 
     per estimate: support index 4, image value 8, row offsets 16, and per row
     entry ray index 4 + length 4 + residual 4; per accepted estimate: per row
-    entry ray index 4 + length 4 + residual read 4 + write 4, image write 8;
-    per residual rebuild (the initial one and every resync): per PILA entry
-    pixel index 4 + length 4 + image value 8, per ray offsets 8 + measured
-    value 8 + residual read 4 + write 4 + squared value 8.
+    entry ray index 4 + length 4 + residual read 4 + write 4, image write 8.
+    The FP64 rebuilds at the resyncs (per PILA entry pixel index 4 + length 4
+    + image value 8, per ray 32) run in their own kernel and are not counted.
     """
-    est = n_steps * M * (28.0 + 12.0 * f_mean)
-    acc = accepts * (8.0 + 16.0 * f_mean)
-    reb = (resyncs + 1) * (16.0 * nnz + 32.0 * G)
-    return est + acc + reb
+    return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
+
+
+# HBM bytes per chain-kernel launch from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs of this benchmark, each scaled by the factor that makes the counter
+# read the known size of a plain device copy in the same run; valid only for
+# the kernel sources they were taken with (hash over the files below)
+TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
+                   "paper_1411_4622_amd/csrc/common.hpp")
+TRAFFIC = {"sources_sha256": "17a08d950e1f7d06f6c480d3aaeb913ed06bd060085ed0ca043f45b7c02b3376",
+           "bytes_per_launch": 143408894.0 + 158822.4}
+
+
+def sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def cpu_baseline(sl, cfg, n_steps_cpu: int) -> dict:
@@ -94,6 +108,9 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (counter "
+                         "calibration for rocprofv3 --pmc runs)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +143,7 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     kernel_ms = []
+    launch_stats = []
     last = {}
 
     def one_step():
@@ -138,6 +156,7 @@ def main() -> int:
         e1.record(stream)
         e1.synchronize()
         kernel_ms.append(e0.elapsed_time(e1))
+        launch_stats.append((st["chain_launches"], st["chain_kernel_ms"]))
         last["stats"] = st
         last["pila"] = (pl.nnz, pl.n_support)
 
@@ -145,6 +164,7 @@ def main() -> int:
         one_step()
         log("warmup %d/%d: chain %.1f ms" % (w + 1, args.warmup, kernel_ms[-1]))
     kernel_ms.clear()
+    launch_stats.clear()
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -158,7 +178,6 @@ def main() -> int:
 
     st = last["stats"]
     nnz, P_sup = last["pila"]
-    G = sl.U * sl.K
     proposals = args.steps * cfg["n_steps"] * cfg["M"]
     value = proposals / wall
     f32_img = img.cpu().numpy()
@@ -176,10 +195,27 @@ def main() -> int:
         rmse64 = datagen.rmse(img64.cpu().numpy(), sl.truth)
         del pl64
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB read + %d MiB written per copy, 3 copies"
+            % (args.copy_probe_mib, args.copy_probe_mib))
+        del src, dst
+
     f_mean = nnz / P_sup
-    kern_s = statistics.mean(kernel_ms) / 1e3
-    alg_bytes = chain_bytes(cfg["n_steps"], cfg["M"], f_mean, st["accepts"], st["resyncs"], nnz, G)
-    achieved = alg_bytes / kern_s / 1e9
+    # chain-kernel launches of the timed steps, each timed by the library with
+    # HIP events on the chain's stream; every step runs the same chain
+    launches = max(int(st["chain_launches"]), 1)
+    launch_s = sum(ms for _, ms in launch_stats) / 1e3 / max(sum(n for n, _ in launch_stats), 1)
+    alg_bytes = chain_kernel_bytes(cfg["n_steps"], cfg["M"], f_mean, st["accepts"]) / launches
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = None
+    if TRAFFIC and TRAFFIC.get("sources_sha256") == sources_hash() and not args.chain_steps:
+        traffic = TRAFFIC["bytes_per_launch"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -214,12 +250,13 @@ def main() -> int:
         "chain": {"accepts": st["accepts"], "accepts_nonzero": st["accepts_nonzero"],
                   "resyncs": st["resyncs"], "T0": st["T0_used"], "max_drift_r": st["max_drift_r"],
                   "max_drift_sse": st["max_drift_sse"], "cost_final": st["cost_final"]},
-        "roofline": {"kernel": "SA chain (sat_segment_kernel segments, FP64 resync kernels "
-                               "between them; one chain per benchmark step)",
+        "roofline": {"kernel": "sat_segment_kernel (one launch per resync segment of the chain)",
                      "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": 1e3 * kern_s,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "traffic": traffic, "launches_per_step": launches,
+                     "avg_launch_ms": 1e3 * launch_s,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "chain_ms_per_step": statistics.mean(kernel_ms)},
         "cpu_baseline": cpu,
         "device": info,
     }

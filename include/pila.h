@@ -80,6 +80,7 @@ typedef struct pila_csr {
     int64_t nnz;       /* out of phase 1 */
     int32_t n_support; /* out of phase 1 */
     int32_t max_row;   /* out of phase 1: longest pixel-major row (entries) */
+    int32_t k_lo, k_hi; /* out of phase 1: bins that support pixels can reach */
     int64_t* row_ptr;
     int32_t* col;
     void* len;
@@ -96,8 +97,8 @@ typedef struct pila_csr {
  * angle, Eq. 5), stored pixel-major and ray-major.
  *
  * Two phases.  Phase 1 (csr->col == NULL): needs csr->row_ptr, csr->trig
- * and csr->t_row_ptr; fills them, sets csr->nnz, csr->n_support and
- * csr->max_row, and synchronises the stream.  pila_build allocates and
+ * and csr->t_row_ptr; fills them, sets csr->nnz, csr->n_support,
+ * csr->max_row and csr->k_lo/k_hi, and synchronises the stream.  pila_build allocates and
  * frees a temporary device buffer of N*N + 256 bytes during each phase.  Phase 2 (csr->col != NULL): needs every array,
  * sized from phase 1; row_ptr/t_row_ptr must still hold phase 1's output.
  * Fills col, len, support, t_col, t_len and synchronises.
@@ -153,6 +154,11 @@ typedef struct sat_stats {
     double cost_final;      /* Eq. 4 of the final image (running value) */
     double max_drift_r;     /* FP32: max |r32 - r64| seen at a resync */
     double max_drift_sse;   /* FP32: max relative |SSE_run - SSE64| at a resync */
+    int32_t chain_launches; /* sat_run: launches of the chain kernel (one, or one
+                               per resync segment); 0 from sat_run_batch */
+    int32_t pad;
+    double chain_kernel_ms; /* sat_run: summed duration of those launches, from
+                               HIP events recorded around each of them */
 } sat_stats;
 
 /* Optional per-step record, device arrays of n_steps elements (each may be

@@ -39,7 +39,7 @@ class CGeom(C.Structure):
 
 class CCsr(C.Structure):
     _fields_ = [("nnz", C.c_int64), ("n_support", C.c_int32), ("max_row", C.c_int32),
-                ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("len", C.c_void_p),
+                ("k_lo", C.c_int32), ("k_hi", C.c_int32), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("len", C.c_void_p),
                 ("support", C.c_void_p), ("trig", C.c_void_p), ("t_row_ptr", C.c_void_p),
                 ("t_col", C.c_void_p), ("t_len", C.c_void_p)]
 
@@ -56,7 +56,8 @@ class CSatStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("accepts", C.c_int64), ("accepts_nonzero", C.c_int64),
                 ("resyncs", C.c_int32), ("status", C.c_int32), ("T0_used", C.c_double),
                 ("TN_used", C.c_double), ("sse_final", C.c_double), ("cost_final", C.c_double),
-                ("max_drift_r", C.c_double), ("max_drift_sse", C.c_double)]
+                ("max_drift_r", C.c_double), ("max_drift_sse", C.c_double),
+                ("chain_launches", C.c_int32), ("pad", C.c_int32), ("chain_kernel_ms", C.c_double)]
 
 
 class CSatTrace(C.Structure):
@@ -168,14 +169,16 @@ class Geometry:
 class Pila:
     """A built PILA: device tensors plus the C descriptor pointing at them."""
 
-    def __init__(self, geom: Geometry, tensors: dict, nnz: int, n_support: int, max_row: int):
+    def __init__(self, geom: Geometry, tensors: dict, nnz: int, n_support: int, max_row: int,
+                 k_lo: int = 0, k_hi: int = -1):
         self.geom = geom
         self.t = tensors
         self.nnz = nnz
         self.n_support = n_support
         self.max_row = max_row
+        self.k_lo, self.k_hi = k_lo, k_hi
         t = tensors
-        self._c = CCsr(nnz, n_support, max_row, _ptr(t["row_ptr"]), _ptr(t["col"]), _ptr(t["len"]),
+        self._c = CCsr(nnz, n_support, max_row, k_lo, k_hi, _ptr(t["row_ptr"]), _ptr(t["col"]), _ptr(t["len"]),
                        _ptr(t["support"]), _ptr(t["trig"]), _ptr(t["t_row_ptr"]), _ptr(t["t_col"]),
                        _ptr(t["t_len"]))
 
@@ -199,10 +202,11 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     row_ptr = torch.empty(NP + 1, dtype=torch.int64, device=dev)
     t_row_ptr = torch.empty(G + 1, dtype=torch.int64, device=dev)
     trig = torch.empty(2 * U, dtype=torch.float64, device=dev)
-    csr = CCsr(0, 0, 0, row_ptr.data_ptr(), None, None, None, trig.data_ptr(), t_row_ptr.data_ptr(),
-               None, None)
+    csr = CCsr(0, 0, 0, 0, -1, row_ptr.data_ptr(), None, None, None, trig.data_ptr(),
+               t_row_ptr.data_ptr(), None, None)
     _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
     nnz, P, max_row = int(csr.nnz), int(csr.n_support), int(csr.max_row)
+    k_lo, k_hi = int(csr.k_lo), int(csr.k_hi)
     ldt = torch.float64 if geom.len_dtype == PILA_F64 else torch.float32
     col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
     ln = torch.empty(max(nnz, 1), dtype=ldt, device=dev)
@@ -215,7 +219,7 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
     return Pila(geom, dict(row_ptr=row_ptr, col=col[:nnz], len=ln[:nnz], support=support[:P],
                            trig=trig, t_row_ptr=t_row_ptr, t_col=t_col[:nnz], t_len=t_ln[:nnz]),
-                nnz, P, max_row)
+                nnz, P, max_row, k_lo, k_hi)
 
 
 def pila_forward(pila: Pila, image, out=None):

@@ -10,6 +10,7 @@
 // single-workgroup scan, and a fill pass that places each wavefront's
 // entries with a lane prefix sum, giving rows in ascending ray (pixel-major)
 // or pixel (ray-major) order without sorting.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -258,8 +259,13 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
 
     std::vector<int32_t> support;
     support.reserve((size_t)NP);
+    double rmax2 = -1.0;  // largest squared distance of a support pixel centre from the axis
     for (int64_t p = 0; p < NP; ++p)
-        if (!geom->mask || geom->mask[p]) support.push_back((int32_t)p);
+        if (!geom->mask || geom->mask[p]) {
+            support.push_back((int32_t)p);
+            const double xc = (double)(p % N) - 0.5 * N + 0.5, yc = 0.5 * N - 0.5 - (double)(p / N);
+            rmax2 = std::max(rmax2, xc * xc + yc * yc);
+        }
 
     // temporary device buffer: [0, 256) small results, [256, 256 + N*N) the mask
     DeviceBuffer tmp;
@@ -299,6 +305,16 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
         csr->nnz = tot[0];
         csr->n_support = (int32_t)support.size();
         csr->max_row = (int32_t)tot[2];
+        // a ray reaches a pixel only within 0.71 of its centre's projection, so
+        // every bin used by the support lies within R + 1 of the detector centre
+        if (rmax2 < 0.0) {
+            csr->k_lo = 0;
+            csr->k_hi = -1;
+        } else {
+            const double R = std::sqrt(rmax2), cK = 0.5 * (K - 1);
+            csr->k_lo = (int32_t)std::max(0.0, std::floor(cK - R - 1.0));
+            csr->k_hi = (int32_t)std::min((double)(K - 1), std::ceil(cK + R + 1.0));
+        }
         return PILA_OK;
     }
 

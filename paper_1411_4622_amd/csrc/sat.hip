@@ -120,45 +120,40 @@ __global__ void sat_final_kernel(ChainJob job)
     st.cost_final = sqrt(fmax(c.sse, 0.0) / KU);
     st.max_drift_r = c.drift_r;
     st.max_drift_sse = c.drift_sse;
+    st.chain_launches = 0;
+    st.pad = 0;
+    st.chain_kernel_ms = 0.0;
     *job.stats = st;
 }
 
 // Persistent batch: each workgroup takes chains from a ticket counter until
-// the tickets run out, so every workgroup reaches the exit.  FP32 chains
-// whose rows and estimates fit the (CPW, E) shape run the pipelined body
-// (residual in global memory, L2-resident), the others the general one;
-// both give the same result.
+// the tickets run out, so every workgroup reaches the exit.  This kernel
+// runs the FP32 chains whose rows and estimates fit the (CPW, E) shape with
+// the pipelined body; sat_batch_simple_kernel runs the others.  Both give the
+// result the chain would give alone.
 template <int CPW, int E>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
-    const ChainJob* __restrict__ jobs, int n_jobs, int* __restrict__ ticket, int lds_bytes)
+    const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
+    int* __restrict__ ticket, int lds_bytes)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    const int NW = blockDim.x >> 6;
+    (void)lds_bytes;
     for (;;) {
         if (threadIdx.x == 0) sh.ticket = atomicAdd(ticket, 1);
         __syncthreads();
         const int j = sh.ticket;
         __syncthreads();
         if (j >= n_jobs) break;
-        const ChainJob J = jobs[j];
-        const int64_t G = (int64_t)J.U * J.K;
-        const bool fits = J.precision == PILA_F32 && J.max_row >= 1 &&
-                          J.max_row <= (kWave / CPW) * E && J.m_cand <= NW * CPW && J.K < 8192 &&
-                          G < (1 << 24);
-        if (fits && 24 * (int64_t)J.U <= lds_bytes) {
-            run_chain_piped<float, false, CPW, E>(J, lds, sh, false);
-        } else if (J.precision == PILA_F32) {
-            run_chain_simple_dispatch<float>(J, lds, lds_bytes, sh);
-        } else {
-            run_chain_simple_dispatch<double>(J, lds, lds_bytes, sh);
-        }
+        const ChainJob J = jobs[order[j]];
+        run_chain_piped<float, false, CPW, E>(J, lds, sh, false);
     }
 }
 
 // Persistent batch for workgroups wider than the pipelined bodies allow:
 // every chain takes the general body.
 __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* __restrict__ jobs,
+                                                                const int* __restrict__ order,
                                                                 int n_jobs, int* __restrict__ ticket,
                                                                 int lds_bytes)
 {
@@ -170,7 +165,7 @@ __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* 
         const int j = sh.ticket;
         __syncthreads();
         if (j >= n_jobs) break;
-        const ChainJob J = jobs[j];
+        const ChainJob J = jobs[order[j]];
         if (J.precision == PILA_F32)
             run_chain_simple_dispatch<float>(J, lds, lds_bytes, sh);
         else
@@ -178,7 +173,11 @@ __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* 
     }
 }
 
-__global__ void zero_int_kernel(int* p) { *p = 0; }
+__global__ void zero_int_kernel(int* p)
+{
+    p[0] = 0;
+    p[1] = 0;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -252,6 +251,19 @@ ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, con
     J.f = image;
     J.max_row = c->max_row;
     J.pad = 0;
+    J.k_lo = c->k_lo;
+    J.Kc = c->k_hi >= c->k_lo ? c->k_hi - c->k_lo + 1 : 0;
+    J.UL = 0;
+    J.pad2 = 0;
+    // g / K for g < 2^24 as (g * m) >> (24 + L), L = ceil(log2 K), m = ceil(2^(24+L) / K):
+    // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K
+    {
+        uint32_t L = 0;
+        while ((1u << L) < (uint32_t)J.K) ++L;
+        const uint64_t den = (uint64_t)1 << (24 + L);
+        J.kdiv_s = 24 + L;
+        J.kdiv_m = (uint32_t)((den + (uint64_t)J.K - 1) / (uint64_t)J.K);
+    }
     const size_t T = (G + 63) / 64;
     J.r = ws;
     J.tsum = (double*)(ws + align256(rs * G));
@@ -324,7 +336,7 @@ const PipedShape* choose_piped(int precision, int m_cand, int max_row, int* wave
     return nullptr;
 }
 
-typedef void (*BatchKernel)(const ChainJob*, int, int*, int);
+typedef void (*BatchKernel)(const ChainJob*, const int*, int, int*, int);
 
 struct BatchShape {
     int cpw, e;
@@ -339,17 +351,66 @@ const std::vector<BatchShape>& batch_shapes()
     return v;
 }
 
+// LDS of a pipelined chain whose residual is not wholly in LDS: the patch
+// table, then as many angles of the residual (over the bins the support
+// reaches) as fit in 'budget'.  Sets J->UL; returns the bytes to request.
+int64_t hybrid_lds(ChainJob* J, int64_t budget)
+{
+    const int64_t rs = J->precision == PILA_F32 ? 4 : 8;
+    const int64_t table = (16 * (int64_t)J->U + 2 * rs * J->U + 15) & ~(int64_t)15;
+    J->UL = 0;
+    if (table > budget) return table;
+    if (J->Kc > 0) {
+        const int64_t ul = (budget - table) / (J->Kc * rs);
+        J->UL = (int32_t)std::min<int64_t>(ul, J->U);
+    }
+    return table + (int64_t)J->UL * J->Kc * rs;
+}
+
 int32_t set_lds(const void* k, int bytes)
 {
     PILA_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return PILA_OK;
 }
 
-int32_t launch1(ChainKernel k, ChainJob* J, int threads, int lds, hipStream_t st)
+// HIP events around each chain-kernel launch of one sat_run, summed after
+// the final synchronisation; inactive when no statistics are requested
+struct LaunchTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    ~LaunchTimer()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    int32_t mark(hipStream_t st)
+    {
+        if (!on) return PILA_OK;
+        hipEvent_t e;
+        PILA_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+        PILA_HIP(hipEventRecord(e, st));
+        return PILA_OK;
+    }
+    int32_t total_ms(double* ms) const
+    {
+        double t = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+            float x = 0.0f;
+            PILA_HIP(hipEventElapsedTime(&x, ev[i], ev[i + 1]));
+            t += x;
+        }
+        *ms = t;
+        return PILA_OK;
+    }
+};
+
+int32_t launch1(ChainKernel k, ChainJob* J, int threads, int lds, hipStream_t st, LaunchTimer* tm)
 {
     PILA_TRY(set_lds((const void*)k, lds));
     void* args[] = {J};
+    PILA_TRY(tm->mark(st));
     PILA_HIP(hipLaunchKernel((const void*)k, dim3(1), dim3(threads), args, (size_t)lds, st));
+    PILA_TRY(tm->mark(st));
     return PILA_OK;
 }
 
@@ -380,6 +441,8 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         return fail(PILA_ENOMEM, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
     hipStream_t st = (hipStream_t)stream;
     ChainJob J = make_job(geom, csr, d_sino, params, d_image, (char*)d_ws);
+    LaunchTimer tm;
+    tm.on = h_stats != nullptr;
     if (trace) {
         J.tr_m = trace->m_star;
         J.tr_acc = trace->accept;
@@ -391,7 +454,7 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     const int rs = params->precision == PILA_F32 ? 4 : 8;
     const int64_t budget = (int64_t)prop.sharedMemPerBlock - (int64_t)sizeof(ChainShared) - 1024;
     const bool r_in_lds = G * rs <= budget;
-    const int table_lds = (int)((16 + rs) * 2 * (int64_t)geom->n_angles);
+    const int table_lds = (int)hybrid_lds(&J, budget);
     int waves = 0;
     const PipedShape* ps =
         piped_allowed(geom, csr) ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
@@ -406,29 +469,34 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         sat_setup_kernel<float><<<1, kPipedThreads, 0, st>>>(J);
         const int64_t n_seg = params->n_steps / params->resync_every + 1;
         for (int64_t k = 0; k < n_seg; ++k) {
-            PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st));
+            PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
             sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 1);
             sat_resync_finish_kernel<<<1, 64, 0, st>>>(J);
         }
         sat_final_kernel<<<1, 1, 0, st>>>(J);
     } else if (ps && (r_in_lds || table_lds <= budget)) {
         const int lds = r_in_lds ? (int)(G * rs) : table_lds;
-        PILA_TRY(launch1(r_in_lds ? ps->k_lds : ps->k_glob, &J, waves * kWave, lds, st));
+        PILA_TRY(launch1(r_in_lds ? ps->k_lds : ps->k_glob, &J, waves * kWave, lds, st, &tm));
     } else {
         waves = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         const int lds = r_in_lds ? (int)(G * rs) : 0;
         if (params->precision == PILA_F64) {
             PILA_TRY(set_lds((const void*)sat_simple_kernel<double>, lds));
+            PILA_TRY(tm.mark(st));
             sat_simple_kernel<double><<<1, waves * kWave, (size_t)lds, st>>>(J, lds);
         } else {
             PILA_TRY(set_lds((const void*)sat_simple_kernel<float>, lds));
+            PILA_TRY(tm.mark(st));
             sat_simple_kernel<float><<<1, waves * kWave, (size_t)lds, st>>>(J, lds);
         }
+        PILA_TRY(tm.mark(st));
     }
     PILA_HIP(hipGetLastError());
     if (h_stats) {
         PILA_HIP(hipMemcpyAsync(h_stats, J.stats, sizeof(sat_stats), hipMemcpyDeviceToHost, st));
         PILA_HIP(hipStreamSynchronize(st));
+        h_stats->chain_launches = (int32_t)(tm.ev.size() / 2);
+        PILA_TRY(tm.total_ms(&h_stats->chain_kernel_ms));
     }
     return PILA_OK;
 }
@@ -437,7 +505,8 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
 {
     clear_error();
     if (n_jobs < 0 || (n_jobs > 0 && !jobs) || !bytes) return fail(PILA_EINVAL, "bad batch arguments");
-    size_t total = align256(sizeof(ChainJob) * (size_t)(n_jobs > 0 ? n_jobs : 1)) + 256;
+    size_t total = align256(sizeof(ChainJob) * (size_t)(n_jobs > 0 ? n_jobs : 1)) +
+                   align256(sizeof(int) * (2 + (size_t)(n_jobs > 0 ? n_jobs : 1)));
     for (int32_t j = 0; j < n_jobs; ++j) {
         PILA_TRY(check_geom(jobs[j].geom));
         total += chain_bytes(jobs[j].geom, &jobs[j].params);
@@ -459,7 +528,7 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     char* ws = (char*)d_ws;
     ChainJob* d_jobs = (ChainJob*)ws;
     int* d_ticket = (int*)(ws + align256(sizeof(ChainJob) * (size_t)n_jobs));
-    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + 256;
+    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (2 + (size_t)n_jobs));
     std::vector<ChainJob> host((size_t)n_jobs);
     int max_m = 1, max_row = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
@@ -482,21 +551,20 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
         return fail(PILA_EINVAL, "waves_per_chain must be 1, 2, 4, 8 or 16");
     if (per_cu < 1 || per_cu > 32) return fail(PILA_EINVAL, "chains_per_cu must be in 1..32");
-    // kernel shape: the fewest estimates per wavefront that cover every FP32
-    // chain's M, then the smallest register row that covers the longest row
+    // pipelined kernel shape: the fewest estimates per wavefront that cover
+    // every FP32 chain's M, then the smallest register row for the longest row
     const BatchShape* bs = nullptr;
     if (waves * kWave <= kPipedThreads) {
         for (int cpw : {1, 2, 4}) {
             if (max_m > waves * cpw) continue;
-            for (const BatchShape& s : batch_shapes()) {
-                if (s.cpw != cpw || max_row > (kWave / cpw) * s.e) continue;
-                bs = &s;
+            for (const BatchShape& sp : batch_shapes()) {
+                if (sp.cpw != cpw || max_row > (kWave / cpw) * sp.e) continue;
+                bs = &sp;
                 break;
             }
             if (bs) break;
         }
     }
-    BatchKernel kern = bs ? bs->k : sat_batch_simple_kernel;  // no shape: the general body
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
     int lds = 0;
@@ -504,16 +572,44 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         const int per_wg = (int)(prop.sharedMemPerBlock / (size_t)per_cu) - (int)sizeof(ChainShared) - 512;
         lds = per_wg > 0 ? (per_wg & ~255) : 0;
     }
-    const int grid_max = prop.multiProcessorCount * per_cu;
-    const int grid = n_jobs < grid_max ? n_jobs : grid_max;
+    // split the chains: pipelined (FP32, fits the shape and the LDS table) and general
+    std::vector<int> piped_ids, simple_ids;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        ChainJob& J = host[j];
+        const int64_t G = (int64_t)J.U * J.K;
+        bool ok = bs && J.precision == PILA_F32 && J.max_row >= 1 &&
+                  J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw &&
+                  J.K < 8192 && G < (1 << 24);
+        if (ok) ok = hybrid_lds(&J, lds) <= lds;  // LDS part of the residual
+        (ok ? piped_ids : simple_ids).push_back(j);
+    }
+    std::vector<int> order(piped_ids);
+    order.insert(order.end(), simple_ids.begin(), simple_ids.end());
+    int* d_order = d_ticket + 2;  // [0]: pipelined ticket, [1]: general ticket, then the order
     PILA_HIP(hipMemcpyAsync(d_jobs, host.data(), sizeof(ChainJob) * host.size(), hipMemcpyHostToDevice, st));
+    PILA_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
     zero_int_kernel<<<1, 1, 0, st>>>(d_ticket);
-    PILA_TRY(set_lds((const void*)kern, lds));
     const ChainJob* jobs_arg = d_jobs;
-    int n_arg = n_jobs, lds_arg = lds;
-    int* ticket_arg = d_ticket;
-    void* args[] = {&jobs_arg, &n_arg, &ticket_arg, &lds_arg};
-    PILA_HIP(hipLaunchKernel((const void*)kern, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
+    int lds_arg = lds;
+    if (!piped_ids.empty()) {
+        int n_arg = (int)piped_ids.size();
+        const int* order_arg = d_order;
+        int* ticket_arg = d_ticket;
+        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
+        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
+        PILA_TRY(set_lds((const void*)bs->k, lds));
+        PILA_HIP(hipLaunchKernel((const void*)bs->k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
+    }
+    if (!simple_ids.empty()) {
+        int n_arg = (int)simple_ids.size();
+        const int* order_arg = d_order + piped_ids.size();
+        int* ticket_arg = d_ticket + 1;
+        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
+        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
+        PILA_TRY(set_lds((const void*)sat_batch_simple_kernel, lds));
+        PILA_HIP(hipLaunchKernel((const void*)sat_batch_simple_kernel, dim3(grid), dim3(waves * kWave), args,
+                                 (size_t)lds, st));
+    }
     PILA_HIP(hipGetLastError());
     if (h_stats) {
         for (int32_t j = 0; j < n_jobs; ++j)

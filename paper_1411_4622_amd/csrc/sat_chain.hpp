@@ -27,8 +27,9 @@
 // xor butterfly with distances 1, 2, 4, 8, 16, 32.  A workgroup of any shape
 // with 16, 32 or 64 lanes per estimate forms exactly these operations (lanes
 // keep 64 / LPC partials), so the result does not depend on the launch shape.
-// Residual rebuilds use one wavefront per ray with the same 64-partial sum,
-// 64-ray tiles summed by the same butterfly, and tiles summed lane-strided.
+// Residual rebuilds sum each ray sequentially over its entries (one lane per
+// ray), 64-ray tiles by the same butterfly, and tiles lane-strided, whether
+// one workgroup or the whole GPU runs them.
 //
 // Visibility: within a workgroup (all waves on one CU, one vector L1) a
 // store issued before s_barrier is seen by loads other waves issue after it,
@@ -53,6 +54,8 @@ struct ChainJob {
     int32_t N, U, K, P;
     int32_t precision, m_cand, n_stages, q_auto;
     int32_t max_row, pad;
+    int32_t k_lo, Kc, UL, pad2;  // LDS part of the residual: angles u < UL, bins k_lo .. k_lo+Kc-1
+    uint32_t kdiv_m, kdiv_s;     // g / K = (g * kdiv_m) >> kdiv_s for g < 2^24
     int64_t n_steps, resync_every;
     uint64_t seed, chain_id;
     double T0, TN, tn_ratio, delta_max, f_min, f_max, ln09;
@@ -260,33 +263,47 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
 }
 
 // One 64-ray tile of a from-scratch FP64 residual r = A f - Pm (Eq. 1,
-// Eq. 4): ray t*64 + j ends in lane j.  Writes r (chain precision), the
-// tile's sum of squares and (if measure) its max |r_old - r64|.
-template <typename Real>
+// Eq. 4): lane j sums ray t*64 + j over its entries in ascending pixel order
+// (fused multiply-add), loading 16 entries at a time so that every lane has
+// many loads in flight.  Writes r (chain precision), the tile's sum of
+// squares (butterfly over the 64 rays) and, if measure, its max |r_old - r64|.
+template <typename Real, int CH = 16>
 __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int t, bool measure,
                              int lane)
 {
+    // CH entries of a ray are loaded at once; the sum runs over them in order,
+    // so CH changes the latency hiding, not the result
     const Real* tl = (const Real*)J.t_len;
-    double mine = 0.0;
-    for (int k = 0; k < kWave; ++k) {
-        const int g = t * kWave + k;
-        if (g >= G) break;
-        const int64_t b = J.t_row_ptr[g], e = J.t_row_ptr[g + 1];
-        double acc = 0.0;
-        for (int64_t q = b + lane; q < e; q += kWave) acc = fma((double)tl[q], J.f[J.t_col[q]], acc);
-        acc = wave_canon_sum(acc);
-        if (lane == k) mine = acc;
-    }
     const int g = t * kWave + lane;
+    double acc = 0.0;
+    if (g < G) {
+        const int64_t b = J.t_row_ptr[g], e = J.t_row_ptr[g + 1];
+        for (int64_t q0 = b; q0 < e; q0 += CH) {
+            int32_t pc[CH];
+            Real lc[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int64_t q = q0 + c < e ? q0 + c : b;
+                pc[c] = J.t_col[q];
+                lc[c] = tl[q];
+            }
+            double fv[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) fv[c] = J.f[pc[c]];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (q0 + c < e) acc = fma((double)lc[c], fv[c], acc);
+        }
+    }
     double sq = 0.0, dr = 0.0;
     if (g < G) {
-        const double r64 = mine - J.sino[g];
+        const double r64 = acc - J.sino[g];
         if (measure) dr = fabs((double)r[g] - r64);
         r[g] = (Real)r64;
         sq = r64 * r64;
     }
     sq = wave_canon_sum(sq);
-    if (measure) dr = wave_min(-dr) * -1.0;  // max over the tile
+    if (measure) dr = -wave_min(-dr);  // max over the tile
     if (lane == 0) {
         J.tsum[t] = sq;
         if (measure) J.tdrift[t] = dr;
@@ -457,6 +474,9 @@ __device__ inline void write_stats(const ChainJob& J, const ChainState& cs)
         st.cost_final = sqrt(fmax(cs.sse, 0.0) / KU);
         st.max_drift_r = cs.drift_r;
         st.max_drift_sse = cs.drift_sse;
+        st.chain_launches = 0;
+        st.pad = 0;
+        st.chain_kernel_ms = 0.0;
         *J.stats = st;
     }
     __syncthreads();
@@ -470,24 +490,37 @@ struct Decision {
 
 // BoME (first minimal S; a NaN never wins) and Step 4's acceptance.  Every
 // wavefront computes the same answer; each lane forms the cost change of its
-// own estimate so the cost arithmetic overlaps the minimum search.
+// own estimate so the cost arithmetic overlaps the minimum search.  The test
+// N1 < exp(-dC / T) is settled by comparing -dC / T with ln N1 (computed
+// ahead of time) whenever they differ by more than 1e-12 relative, far
+// beyond the rounding of exp, the division and the logarithm; inside that
+// band (and for N1 = 0) it is evaluated exactly as written.
 __device__ __forceinline__ Decision decide(const double* S, int M, int lane, double sse, double co,
-                                           double KU, double T, double N1)
+                                           double KU, double T, double invT, double N1, double lnN1)
 {
     double v = lane < M ? S[lane] : INFINITY;
     if (v != v) v = INFINITY;
     const double cn = sqrt(fmax(sse + v, 0.0) / KU);
     const double den = cn + co;
     const double dC = den == 0.0 ? 0.0 : (v / KU) / den;
-    const double ex = exp(-dC / T);
     const double vmin = wave_min(v);
     const unsigned long long mask = __ballot(v == vmin);
     Decision dn;
     dn.ms = mask ? uniform_i32(__ffsll((long long)mask) - 1) : 0;
     dn.S = readlane_f64(v, dn.ms);
     dn.dC = readlane_f64(dC, dn.ms);
-    const double ex_s = readlane_f64(ex, dn.ms);
-    dn.accept = (dn.dC <= 0.0) || (N1 < ex_s);
+    if (dn.dC <= 0.0) {
+        dn.accept = true;
+    } else {
+        const double x = -dn.dC * invT;
+        const double margin = 1e-12 * (fabs(lnN1) + fabs(x));
+        if (N1 > 0.0 && x < lnN1 - margin)
+            dn.accept = false;
+        else if (N1 > 0.0 && x > lnN1 + margin)
+            dn.accept = true;
+        else
+            dn.accept = N1 < exp(-dn.dC / T);
+    }
     return dn;
 }
 
@@ -554,8 +587,9 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
         }
         const double co = sqrt(cs.sse / KU);
         const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+        const double lnN1 = log(N1), invT = 1.0 / T;
         __syncthreads();
-        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, N1);
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, N1, lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
         if (dn.accept && wave == dn.ms % NW) {  // the owner of the winner applies Eq. 6
             const int32_t p = sh.p[dn.ms];
@@ -583,35 +617,65 @@ template <typename Real, int E>
 struct RowSet {
     int32_t col[E];
     Real len[E];
-    int32_t tk[E];  // global-residual mode: (2 u + k % 2) << 13 | k of each ray
+    int32_t tk[E];  // where each ray's residual lives: LDS index (flagged) or patch slot
+    Real rv[E];     // residual values of the row's rays
+    double fo;      // image value of the pixel
     int32_t p, n;   // pixel, row length
     double delta;   // proposed change before the clamp
     double N1;      // acceptance uniform of the step
+    double lnN1;
 };
 
 struct Draws {  // one block of steps: lane j <-> (step j / CPW, estimate slot j % CPW)
     int64_t base;
     int64_t b;
     int32_t p, n;
-    double delta, N1;
+    double delta, N1, lnN1;
 };
+
+// LDS part of the residual (global mode): angles u < UL, bins k_lo ..
+// k_lo + Kc - 1, stored densely; the rest of the residual stays in global
+// memory.  Loaded after every rebuild, written back before every rebuild
+// and at the end so the global copy is complete whenever it is read whole.
+template <typename Real>
+__device__ void lds_residual_load(const ChainJob& J, const Real* r, Real* rl)
+{
+    const int n = J.UL * J.Kc;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int u = i / J.Kc, k = J.k_lo + i % J.Kc;
+        rl[i] = r[u * J.K + k];
+    }
+}
+template <typename Real>
+__device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
+{
+    const int n = J.UL * J.Kc;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int u = i / J.Kc, k = J.k_lo + i % J.Kc;
+        r[u * J.K + k] = rl[i];
+    }
+}
 
 template <typename Real, bool RLDS, int CPW, int E>
 __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int LPC = kWave / CPW;  // lanes per estimate
     constexpr int BL = kWave / CPW;   // steps per block of draws
+    constexpr int kLdsFlag = (int)0x80000000;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
     const int slot = lane / LPC, li = lane % LPC;
     const double KU = (double)J.K * (double)J.U;
     const int M = J.m_cand;
     const int m_mine = wave * CPW + slot;
     const bool active = m_mine < M;
-    const int G = J.U * J.K;
+    // RLDS: the whole residual lives in LDS.  Otherwise the residual is in
+    // global memory except angles u < UL, which live in LDS (rl); rvB holds
+    // the global values one step ahead and the table of the last accepted
+    // row's new global values patches them.
     Real* r = RLDS ? (Real*)lds : (Real*)J.r;
-    // global-residual mode: table of the last accepted row's new residuals
     int64_t* pkey = (int64_t*)lds;
     Real* pval = (Real*)(lds + 16 * (size_t)J.U);
+    Real* rl = (Real*)(lds + ((16 * (size_t)J.U + 2 * sizeof(Real) * (size_t)J.U + 15) & ~(size_t)15));
     const Real* lenp = (const Real*)J.len;
 
     ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
@@ -619,10 +683,10 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) {
         for (int q = threadIdx.x; q < 2 * J.U; q += blockDim.x) pkey[q] = -1;
+        lds_residual_load<Real>(J, r, rl);
     }
     Schedule sched;
     sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN);
-    const float invK = 1.0f / (float)J.K;
 
     Draws cur, nxt;
     auto fill = [&](Draws& D, int64_t base) {
@@ -634,6 +698,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         D.b = 0;
         D.delta = 0.0;
         D.N1 = 0.0;
+        D.lnN1 = 0.0;
         if (s < n_steps) {
             if (m < M) {
                 const Words4 w = philox4x64(J.seed, J.chain_id, (uint64_t)s, (uint64_t)m, 0, 0);
@@ -642,7 +707,10 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 D.b = J.row_ptr[D.p];
                 D.n = (int32_t)(J.row_ptr[D.p + 1] - D.b);
             }
-            if (lane % CPW == 0) D.N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+            if (lane % CPW == 0) {
+                D.N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+                D.lnN1 = log(D.N1);
+            }
         }
     };
     cur.base = nxt.base = -1;
@@ -653,6 +721,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             S.n = 0;
             S.delta = 0.0;
             S.N1 = 0.0;
+            S.lnN1 = 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 S.col[e] = 0;
@@ -676,6 +745,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         const int64_t b = __shfl(cur.b, src, kWave);
         S.delta = __shfl(cur.delta, src, kWave);
         S.N1 = __shfl(cur.N1, j * CPW, kWave);
+        S.lnN1 = __shfl(cur.lnN1, j * CPW, kWave);
         // loads are unconditional (entries past the row read entry 0) so that
         // nothing waits for them here; validity is tested where they are used
 #pragma unroll
@@ -686,108 +756,134 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             S.len[e] = lenp[at];
         }
     };
-    // ray -> patch-table slot; needs the row's ray indices to have arrived
+    // where each ray of a row lives: LDS index (flagged) or patch-table slot
     auto table_slots = [&](RowSet<Real, E>& S) {
         if (RLDS) return;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int g = S.col[e];
-            int u = (int)((float)g * invK);
-            int k = g - u * J.K;
-            if (k < 0) {
-                --u;
-                k += J.K;
-            } else if (k >= J.K) {
-                ++u;
-                k -= J.K;
-            }
-            S.tk[e] = ((2 * u + (k & 1)) << 13) | k;
+            const int u = (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s);  // g / K, g < 2^24
+            const int k = g - u * J.K;
+            const int kk = k - J.k_lo;
+            if (u < J.UL && kk >= 0 && kk < J.Kc)
+                S.tk[e] = kLdsFlag | (u * J.Kc + kk);
+            else
+                S.tk[e] = ((2 * u + (k & 1)) << 13) | k;
         }
     };
+    auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
 
     RowSet<Real, E> A, B, C;
-    Real rvA[E], rvB[E];
-    double foA = 0.0, foB = 0.0;
     prefetch(A, s_begin);
     prefetch(B, s_begin + 1);
-    __syncthreads();  // setup (residual, temperatures, patch table) complete
+    __syncthreads();  // setup (residual, LDS part, temperatures, patch table) complete
     table_slots(A);
 #pragma unroll
-    for (int e = 0; e < E; ++e) rvA[e] = r[A.col[e]];
-    foA = J.f[A.p];
-    bool patch = false;     // apply the table of step s - 1 to rvA
+    for (int e = 0; e < E; ++e) A.rv[e] = in_lds(A.tk[e]) ? rl[A.tk[e] & ~kLdsFlag] : r[A.col[e]];
+    A.fo = J.f[A.p];
+    bool patch = false;     // apply the table of step s - 1 to X.rv
     int32_t lp = -1;        // last accepted pixel (step s - 1) and its value
     double lfn = 0.0;
 
-    for (int64_t s = s_begin; s < n_steps; ++s) {
+    // One step with X the estimates of step s, Y those of s + 1 (their
+    // global operands are loaded here) and Z those of s + 2 (rows loaded
+    // here).  The loop below rotates the roles, so no registers are copied.
+    // Returns true when a segmented chain must stop for a resync.
+    auto step = [&](RowSet<Real, E>& X, RowSet<Real, E>& Y, RowSet<Real, E>& Z, int64_t s)
+                    __attribute__((always_inline)) -> bool {
         const double T = sched.at(s, n_steps, J.n_stages);
-        // operands of this step: patch with the previous step's change
-        if (!RLDS && patch) {
+        const double invT = 1.0 / T;
+        if (!RLDS && patch) {  // the previous step's accepted change
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int tk = A.tk[e];
-                const int64_t key = pkey[tk >> 13];
-                if (key == (((int64_t)(s - 1)) << 13 | (tk & 8191))) rvA[e] = pval[tk >> 13];
+                const int tk = X.tk[e];
+                if (!(tk & kLdsFlag)) {
+                    const int64_t key = pkey[tk >> 13];
+                    if (key == (((int64_t)(s - 1)) << 13 | (tk & 8191))) X.rv[e] = pval[tk >> 13];
+                }
             }
         }
-        if (A.p == lp) foA = lfn;
-        double fn = foA + A.delta;
+        if (X.p == lp) X.fo = lfn;
+        double fn = X.fo + X.delta;
         if (fn < J.f_min) fn = J.f_min;
         if (fn > J.f_max) fn = J.f_max;
-        const double d = fn - foA;
+        const double d = fn - X.fo;
         const Real dr = (Real)d;
         Real part[CPW];
 #pragma unroll
         for (int k = 0; k < CPW; ++k) part[k] = (Real)0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const Real t = (li + e * LPC < A.n) ? dr * A.len[e] : (Real)0;
-            part[e % CPW] = fma(t, (Real)2 * rvA[e] + t, part[e % CPW]);
+            const Real t = (li + e * LPC < X.n) ? dr * X.len[e] : (Real)0;
+            part[e % CPW] = fma(t, (Real)2 * X.rv[e] + t, part[e % CPW]);
         }
         const Real S = canon_sum<LPC>(part);
         if (active && li == 0) {
             sh.S[m_mine] = (double)S;
             sh.d[m_mine] = d;
         }
-        // next step's operands (issued before the row loads of step s + 2)
-        table_slots(B);
+        // next step's global operands (issued before the row loads of step s + 2)
+        table_slots(Y);
         if (!RLDS) {
+            // every entry is written, so the set's values of two steps ago die here
 #pragma unroll
-            for (int e = 0; e < E; ++e) rvB[e] = r[B.col[e]];
+            for (int e = 0; e < E; ++e) {
+                Y.rv[e] = (Real)0;
+                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = r[Y.col[e]];
+            }
         }
-        foB = J.f[B.p];
-        prefetch(C, s + 2);
+        Y.fo = J.f[Y.p];
+        prefetch(Z, s + 2);
         const double co = sqrt(cs.sse / KU);
         __syncthreads();
-        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, A.N1);
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, X.N1, X.lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
         if (dn.accept && dn.ms == m_mine) {  // the owner of the winner applies Eq. 6
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                if (li + e * LPC < A.n) {
-                    const Real rn = rvA[e] + dr * A.len[e];
-                    r[A.col[e]] = rn;
-                    if (!RLDS) {
-                        pkey[A.tk[e] >> 13] = ((int64_t)s << 13) | (A.tk[e] & 8191);
-                        pval[A.tk[e] >> 13] = rn;
+                if (li + e * LPC < X.n) {
+                    const Real rn = X.rv[e] + dr * X.len[e];
+                    if (RLDS) {
+                        r[X.col[e]] = rn;
+                    } else if (X.tk[e] & kLdsFlag) {
+                        rl[X.tk[e] & ~kLdsFlag] = rn;
+                    } else {
+                        r[X.col[e]] = rn;
+                        pkey[X.tk[e] >> 13] = ((int64_t)s << 13) | (X.tk[e] & 8191);
+                        pval[X.tk[e] >> 13] = rn;
                     }
                 }
             }
             if (li == 0) {
-                J.f[A.p] = fn;
-                sh.pstar = A.p;
+                J.f[X.p] = fn;
+                sh.pstar = X.p;
                 sh.fnstar = fn;
             }
         }
         count_decision(J, cs, dn, d_star, s);
-        bool resynced = false;
         if (sizeof(Real) == 4 && J.resync_every > 0 && cs.since >= J.resync_every) {
+            if (!RLDS) {
+                __syncthreads();
+                lds_residual_store<Real>(J, r, rl);
+            }
             if (segmented) {  // the FP64 rebuild runs grid-wide between launches
                 save_carry(J, cs, s + 1, true);
-                return;
+                return true;
             }
             resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
-            resynced = true;
+            if (!RLDS) lds_residual_load<Real>(J, r, rl);
+            // the next two sets are drawn again after the rebuild, so that no
+            // row stays in registers across it
+            prefetch(Y, s + 1);
+            prefetch(Z, s + 2);
+            table_slots(Y);
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) Y.rv[e] = in_lds(Y.tk[e]) ? rl[Y.tk[e] & ~kLdsFlag] : r[Y.col[e]];
+            Y.fo = J.f[Y.p];
+            lp = -1;
+            patch = false;
+            return false;
         }
         __syncthreads();
         if (dn.accept) {
@@ -796,21 +892,29 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         } else {
             lp = -1;
         }
-        patch = dn.accept && !resynced;
-        A = B;
-        B = C;
-        foA = foB;
-        if (RLDS || resynced) {
+        patch = dn.accept;
+        // operands of step s + 1 that live in LDS
 #pragma unroll
-            for (int e = 0; e < E; ++e) rvA[e] = r[A.col[e]];
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) rvA[e] = rvB[e];
+        for (int e = 0; e < E; ++e) {
+            if (in_lds(Y.tk[e]))
+                Y.rv[e] = rl[Y.tk[e] & ~kLdsFlag];
+            else if (RLDS)
+                Y.rv[e] = r[Y.col[e]];
         }
-        if (resynced) {
-            foA = J.f[A.p];
-            lp = -1;
-        }
+        return false;
+    };
+
+    for (int64_t s = s_begin; s < n_steps;) {
+        if (step(A, B, C, s)) return;
+        if (++s >= n_steps) break;
+        if (step(B, C, A, s)) return;
+        if (++s >= n_steps) break;
+        if (step(C, A, B, s)) return;
+        ++s;
+    }
+    if (!RLDS) {
+        __syncthreads();
+        lds_residual_store<Real>(J, r, rl);
     }
     if (segmented) {
         save_carry(J, cs, n_steps, false);

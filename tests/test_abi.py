@@ -85,7 +85,7 @@ def test_bad_sat_arguments(P):
     rc = lib.sat_run(C.byref(g.c), C.byref(csr), None, C.byref(prm), None, None, 0, None, None, None)
     assert rc == P._binding.PILA_EINVAL
     fake = 0x1000
-    csr = CCsr(10, 5, 4, fake, fake, fake, fake, fake, fake, fake, fake)
+    csr = CCsr(10, 5, 4, 0, 3, fake, fake, fake, fake, fake, fake, fake, fake)
     for bad in (dict(m_cand=0), dict(m_cand=65), dict(n_stages=0), dict(precision="f32"),
                 dict(T0=None, q_auto=0), dict(T0=1.0, TN=-1.0), dict(delta_max=float("nan")),
                 dict(f_min=1.0, f_max=0.0), dict(n_steps=-1)):
