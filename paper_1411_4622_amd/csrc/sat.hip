@@ -315,8 +315,12 @@ const std::vector<PipedShape>& piped_shapes(int precision)
 
 bool piped_allowed(const pila_geom* g, const pila_csr* c)
 {
+    // ray index g = u K + k below 2^24 (the multiply-shift split), bins
+    // below 8192 (the patch-table tag), and 32-bit byte offsets into the rows
     const int64_t G = (int64_t)g->n_angles * g->n_bins;
-    return c->nnz >= 1 && c->max_row >= 1 && g->n_bins < 8192 && G < (1 << 24);
+    const int64_t lb = g->len_dtype == PILA_F32 ? 4 : 8;
+    return c->nnz >= 1 && c->max_row >= 1 && g->n_bins < 8192 && G < (1 << 24) &&
+           c->nnz * lb <= ((int64_t)1 << 32);
 }
 
 // Pick the pipelined shape for one chain: the fewest estimates per
@@ -576,10 +580,8 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     std::vector<int> piped_ids, simple_ids;
     for (int32_t j = 0; j < n_jobs; ++j) {
         ChainJob& J = host[j];
-        const int64_t G = (int64_t)J.U * J.K;
-        bool ok = bs && J.precision == PILA_F32 && J.max_row >= 1 &&
-                  J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw &&
-                  J.K < 8192 && G < (1 << 24);
+        bool ok = bs && J.precision == PILA_F32 && piped_allowed(jobs[j].geom, jobs[j].csr) &&
+                  J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw;
         if (ok) ok = hybrid_lds(&J, lds) <= lds;  // LDS part of the residual
         (ok ? piped_ids : simple_ids).push_back(j);
     }

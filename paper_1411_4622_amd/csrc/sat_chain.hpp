@@ -613,6 +613,20 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
 // ---------------------------------------------------------------------------
 // pipelined: rows in registers two steps ahead, operands one step ahead
 // ---------------------------------------------------------------------------
+// element i of a global array through a 32-bit byte offset from a uniform
+// base (one address register per load); the host keeps every such array
+// below 4 GiB
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t i)
+{
+    return *(const T*)((const char*)base + i * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, uint32_t i, T v)
+{
+    *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
+}
+
 template <typename Real, int E>
 struct RowSet {
     int32_t col[E];
@@ -628,7 +642,7 @@ struct RowSet {
 
 struct Draws {  // one block of steps: lane j <-> (step j / CPW, estimate slot j % CPW)
     int64_t base;
-    int64_t b;
+    uint32_t b;
     int32_t p, n;
     double delta, N1, lnN1;
 };
@@ -699,16 +713,21 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         D.delta = 0.0;
         D.N1 = 0.0;
         D.lnN1 = 0.0;
+        // the key is made opaque here, so that the round keys are formed per
+        // block instead of being held in scalar registers across the loop
+        uint64_t k0 = J.seed, k1 = J.chain_id;
+        asm volatile("" : "+s"(k0), "+s"(k1));
         if (s < n_steps) {
             if (m < M) {
-                const Words4 w = philox4x64(J.seed, J.chain_id, (uint64_t)s, (uint64_t)m, 0, 0);
+                const Words4 w = philox4x64(k0, k1, (uint64_t)s, (uint64_t)m, 0, 0);
                 D.p = J.support[__umul64hi(w.w0, (uint64_t)J.P)];
                 D.delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
-                D.b = J.row_ptr[D.p];
-                D.n = (int32_t)(J.row_ptr[D.p + 1] - D.b);
+                const int64_t b0 = J.row_ptr[D.p];
+                D.b = (uint32_t)b0;
+                D.n = (int32_t)(J.row_ptr[D.p + 1] - b0);
             }
             if (lane % CPW == 0) {
-                D.N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+                D.N1 = unit53(philox4x64(k0, k1, (uint64_t)s, 0, 1, 0).w0);
                 D.lnN1 = log(D.N1);
             }
         }
@@ -742,7 +761,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         const int src = j * CPW + slot;
         S.p = __shfl(cur.p, src, kWave);
         S.n = __shfl(cur.n, src, kWave);
-        const int64_t b = __shfl(cur.b, src, kWave);
+        const uint32_t b = (uint32_t)__shfl((int)cur.b, src, kWave);
         S.delta = __shfl(cur.delta, src, kWave);
         S.N1 = __shfl(cur.N1, j * CPW, kWave);
         S.lnN1 = __shfl(cur.lnN1, j * CPW, kWave);
@@ -751,9 +770,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int q = li + e * LPC;
-            const int64_t at = q < S.n ? b + q : 0;
-            S.col[e] = J.col[at];
-            S.len[e] = lenp[at];
+            const uint32_t at = q < S.n ? b + (uint32_t)q : 0u;
+            S.col[e] = ld32(J.col, at);
+            S.len[e] = ld32(lenp, at);
         }
     };
     // where each ray of a row lives: LDS index (flagged) or patch-table slot
@@ -772,6 +791,8 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         }
     };
     auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
+    // residual value of ray g outside the LDS part
+    auto rget = [&](int32_t g) -> Real { return RLDS ? r[g] : ld32((const Real*)r, (uint32_t)g); };
 
     RowSet<Real, E> A, B, C;
     prefetch(A, s_begin);
@@ -779,7 +800,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     __syncthreads();  // setup (residual, LDS part, temperatures, patch table) complete
     table_slots(A);
 #pragma unroll
-    for (int e = 0; e < E; ++e) A.rv[e] = in_lds(A.tk[e]) ? rl[A.tk[e] & ~kLdsFlag] : r[A.col[e]];
+    for (int e = 0; e < E; ++e) A.rv[e] = in_lds(A.tk[e]) ? rl[A.tk[e] & ~kLdsFlag] : rget(A.col[e]);
     A.fo = J.f[A.p];
     bool patch = false;     // apply the table of step s - 1 to X.rv
     int32_t lp = -1;        // last accepted pixel (step s - 1) and its value
@@ -829,7 +850,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 Y.rv[e] = (Real)0;
-                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = r[Y.col[e]];
+                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = rget(Y.col[e]);
             }
         }
         Y.fo = J.f[Y.p];
@@ -838,7 +859,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         __syncthreads();
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, X.N1, X.lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
-        if (dn.accept && dn.ms == m_mine) {  // the owner of the winner applies Eq. 6
+        // an accepted zero change leaves image and residual as they are
+        const bool changed = dn.accept && d_star != 0.0;
+        if (changed && dn.ms == m_mine) {  // the owner of the winner applies Eq. 6
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (li + e * LPC < X.n) {
@@ -848,7 +871,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                     } else if (X.tk[e] & kLdsFlag) {
                         rl[X.tk[e] & ~kLdsFlag] = rn;
                     } else {
-                        r[X.col[e]] = rn;
+                        st32(r, (uint32_t)X.col[e], rn);
                         pkey[X.tk[e] >> 13] = ((int64_t)s << 13) | (X.tk[e] & 8191);
                         pval[X.tk[e] >> 13] = rn;
                     }
@@ -879,27 +902,27 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             table_slots(Y);
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < E; ++e) Y.rv[e] = in_lds(Y.tk[e]) ? rl[Y.tk[e] & ~kLdsFlag] : r[Y.col[e]];
+            for (int e = 0; e < E; ++e) Y.rv[e] = in_lds(Y.tk[e]) ? rl[Y.tk[e] & ~kLdsFlag] : rget(Y.col[e]);
             Y.fo = J.f[Y.p];
             lp = -1;
             patch = false;
             return false;
         }
         __syncthreads();
-        if (dn.accept) {
+        if (changed) {
             lp = uniform_i32(sh.pstar);
             lfn = uniform_f64(sh.fnstar);
         } else {
             lp = -1;
         }
-        patch = dn.accept;
+        patch = changed;
         // operands of step s + 1 that live in LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if (in_lds(Y.tk[e]))
                 Y.rv[e] = rl[Y.tk[e] & ~kLdsFlag];
             else if (RLDS)
-                Y.rv[e] = r[Y.col[e]];
+                Y.rv[e] = rget(Y.col[e]);
         }
         return false;
     };
