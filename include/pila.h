@@ -259,6 +259,104 @@ int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const double* d_sin
 /* Device information and errors                                             */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Serving: many independent chains (one slice each, section II-A Steps 1-4  */
+/* per slice) admitted against a memory budget and run by resident          */
+/* workgroups that take new requests as earlier ones finish                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct srv_s srv_t; /* opaque server handle */
+
+typedef struct srv_config {
+    size_t mem_budget;       /* device bytes the server allocates at creation and never
+                                exceeds: PILA cache, chain states, build scratch */
+    int32_t max_slots;       /* chains resident at once, one workgroup each;
+                                0 = compute units - 8 (the rest stay free for PILA builds) */
+    int32_t waves_per_chain; /* 4 or 8 (0 = 8) */
+    int32_t ring_size;       /* tickets submitted and not yet reaped; power of two, 0 = 1024 */
+    int32_t idle_us;         /* a workgroup that finds no work for this long exits; the
+                                server relaunches on the next submission (0 = 20000) */
+} srv_config;
+
+typedef struct srv_request {
+    const pila_geom* geom;   /* host; len_dtype must equal params.precision.  The server
+                                builds the PILA on first use and caches it */
+    const double* d_sino;    /* device [U*K], caller-owned, unchanged until reaped */
+    double* d_image;         /* device [N*N]: f0 in, the chain's final image out;
+                                caller-owned, untouched by others until reaped */
+    sat_params params;       /* as for sat_run */
+} srv_request;
+
+typedef struct srv_status {
+    int64_t submitted;       /* tickets issued */
+    int64_t reaped;          /* tickets whose results were returned by srv_poll */
+    int64_t in_flight;       /* issued, not yet reaped */
+    int64_t launches;        /* launches of the resident kernel so far */
+    size_t bytes_used;       /* of mem_budget */
+    size_t bytes_budget;
+    int32_t pila_cached;     /* geometries whose PILA is resident */
+    int32_t kernel_running;  /* the resident kernel has not exited yet */
+} srv_status;
+
+/*
+ * srv_create - allocate the server on the current device: mem_budget bytes
+ * of device memory, a ring of ring_size request descriptors in pinned host
+ * memory, and non-blocking streams for the resident kernels.  No device
+ * memory is allocated after this call (PILA builds use the budget too).
+ * The resident kernels run while requests are in flight and for idle_us
+ * after: a device-wide synchronisation (hipDeviceSynchronize) waits for
+ * them, so callers synchronise their own streams instead.
+ * Errors: EINVAL (NULL arguments, bad sizes), ENOMEM (budget too small for
+ * the server's own bookkeeping), EHIP.
+ */
+int32_t srv_create(const srv_config* cfg, srv_t** out);
+
+/*
+ * srv_prepare - build and cache the PILA of a geometry now (Eq. 5), so that
+ * later submissions of that geometry do not build.  Synchronises the
+ * server's build stream.  ENOMEM when it cannot fit even after evicting
+ * every unused cached PILA.
+ */
+int32_t srv_prepare(srv_t* s, const pila_geom* geom);
+
+/*
+ * srv_submit - admit one chain.  Its sinogram and starting image must be
+ * complete in device memory when this is called (the work that wrote them
+ * has finished).  Admission needs the geometry's PILA (built
+ * if absent, evicting least recently used PILAs that no admitted request
+ * uses) and chain state of sat_workspace_size bytes inside the budget, and
+ * a free ring slot.  On success *ticket names the request; its chain is
+ * taken by the next free resident workgroup in ticket order.
+ * Errors: EBUSY when not admissible now (retry after reaping others),
+ * EINVAL (as sat_run), ENOMEM when the request could never fit the budget.
+ */
+int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket);
+
+/*
+ * srv_poll - *done = 1 and *stats (nullable) filled when the ticket's chain
+ * has finished; its image is then final in d_image and the ticket is reaped
+ * (its memory returns to the budget).  *done = 0 otherwise.  Also relaunches
+ * the resident kernel when it has exited with requests still waiting.
+ * ENOTFOUND for unknown or already reaped tickets.
+ */
+int32_t srv_poll(srv_t* s, uint64_t ticket, int32_t* done, sat_stats* stats);
+
+/*
+ * srv_cancel - ask the ticket's chain to stop: a waiting chain never starts,
+ * a running one stops within 2048 steps.  Either way srv_poll then reports
+ * it done with stats.status = PILA_ECANCELED (the image holds the state
+ * reached).  ENOTFOUND for unknown or reaped tickets.
+ */
+int32_t srv_cancel(srv_t* s, uint64_t ticket);
+
+int32_t srv_get_status(srv_t* s, srv_status* st);
+
+/*
+ * srv_destroy - cancel what still runs, wait for the resident kernel to
+ * exit, and free everything.  NULL is accepted.
+ */
+int32_t srv_destroy(srv_t* s);
+
 typedef struct pila_device_info {
     int32_t cu_count;
     int32_t lds_per_block;   /* bytes */

@@ -23,7 +23,8 @@ PILA_F64, PILA_F32 = 0, 1
 
 EXPORTED = ["pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run",
             "sat_batch_workspace_size", "sat_run_batch", "sirt_workspace_size", "sirt_run",
-            "pila_get_device_info", "pila_last_error"]
+            "srv_create", "srv_prepare", "srv_submit", "srv_poll", "srv_cancel", "srv_get_status",
+            "srv_destroy", "pila_get_device_info", "pila_last_error"]
 
 
 class PilaError(RuntimeError):
@@ -78,6 +79,22 @@ class CSirtParams(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double)]
 
 
+class CSrvConfig(C.Structure):
+    _fields_ = [("mem_budget", C.c_size_t), ("max_slots", C.c_int32), ("waves_per_chain", C.c_int32),
+                ("ring_size", C.c_int32), ("idle_us", C.c_int32)]
+
+
+class CSrvRequest(C.Structure):
+    _fields_ = [("geom", C.POINTER(CGeom)), ("d_sino", C.c_void_p), ("d_image", C.c_void_p),
+                ("params", CSatParams)]
+
+
+class CSrvStatus(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("reaped", C.c_int64), ("in_flight", C.c_int64),
+                ("launches", C.c_int64), ("bytes_used", C.c_size_t), ("bytes_budget", C.c_size_t),
+                ("pila_cached", C.c_int32), ("kernel_running", C.c_int32)]
+
+
 class CDeviceInfo(C.Structure):
     _fields_ = [("cu_count", C.c_int32), ("lds_per_block", C.c_int32), ("clock_khz", C.c_int32),
                 ("warp_size", C.c_int32), ("hbm_bytes", C.c_size_t), ("name", C.c_char * 64)]
@@ -108,6 +125,13 @@ def load(path: str = LIB_PATH):
                                   C.POINTER(CSatStats), V]
     lib.sirt_workspace_size.argtypes = [G, C.POINTER(CSirtParams), C.POINTER(C.c_size_t)]
     lib.sirt_run.argtypes = [G, CS, V, C.POINTER(CSirtParams), V, V, C.c_size_t, V, V]
+    lib.srv_create.argtypes = [C.POINTER(CSrvConfig), C.POINTER(V)]
+    lib.srv_prepare.argtypes = [V, G]
+    lib.srv_submit.argtypes = [V, C.POINTER(CSrvRequest), C.POINTER(C.c_uint64)]
+    lib.srv_poll.argtypes = [V, C.c_uint64, C.POINTER(I32), C.POINTER(CSatStats)]
+    lib.srv_cancel.argtypes = [V, C.c_uint64]
+    lib.srv_get_status.argtypes = [V, C.POINTER(CSrvStatus)]
+    lib.srv_destroy.argtypes = [V]
     lib.pila_get_device_info.argtypes = [C.POINTER(CDeviceInfo)]
     lib.pila_last_error.restype = C.c_char_p
     for name in EXPORTED:
@@ -368,6 +392,79 @@ def sirt_run(pila: Pila, sino, n_iter: int, lam: float, image, workspace=None,
                         workspace.data_ptr(), workspace.numel(),
                         costs.ctypes.data if costs is not None else None, _stream()))
     return costs[:n_iter] if costs is not None else None
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+
+class Server:
+    """Chains admitted against a device-memory budget and run by resident
+    workgroups that take new requests as earlier ones finish (srv_* ABI).
+
+    submit() returns a ticket, or None when the request is not admissible now
+    (EBUSY); poll() returns None while the chain runs, else its stats (the
+    image is final then).  The sinogram and image tensors are kept alive
+    until their ticket is reaped.
+    """
+
+    def __init__(self, mem_budget: int, max_slots: int = 0, waves_per_chain: int = 0,
+                 ring_size: int = 0, idle_us: int = 0):
+        cfg = CSrvConfig(int(mem_budget), int(max_slots), int(waves_per_chain), int(ring_size),
+                         int(idle_us))
+        h = C.c_void_p()
+        _check(load().srv_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def prepare(self, geom: Geometry):
+        _check(load().srv_prepare(self._h, C.byref(geom.c)))
+
+    def submit(self, geom: Geometry, sino, image, params: SatParams) -> Optional[int]:
+        assert sino.is_contiguous() and image.is_contiguous()
+        req = CSrvRequest(C.pointer(geom.c), sino.data_ptr(), image.data_ptr(), params.c())
+        t = C.c_uint64(0)
+        rc = load().srv_submit(self._h, C.byref(req), C.byref(t))
+        if rc == PILA_EBUSY:
+            return None
+        _check(rc)
+        self._held[t.value] = (geom, sino, image)
+        return t.value
+
+    def poll(self, ticket: int) -> Optional[dict]:
+        done = C.c_int32(0)
+        st = CSatStats()
+        _check(load().srv_poll(self._h, ticket, C.byref(done), C.byref(st)))
+        if not done.value:
+            return None
+        self._held.pop(ticket, None)
+        return _stats_dict(st)
+
+    def cancel(self, ticket: int):
+        _check(load().srv_cancel(self._h, ticket))
+
+    def status(self) -> dict:
+        st = CSrvStatus()
+        _check(load().srv_get_status(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in CSrvStatus._fields_}
+
+    def close(self):
+        if self._h:
+            _check(load().srv_destroy(self._h))
+            self._h = None
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_info() -> dict:

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "sat_host.hpp"
 
 namespace pila {
 
@@ -246,6 +247,8 @@ void launch_fill(const pila_geom* g, pila_csr* csr, const uint8_t* dmask, hipStr
 
 using namespace pila;
 
+size_t pila::pila_build_scratch(const pila_geom* geom) { return 256 + (size_t)geom->n * (size_t)geom->n; }
+
 extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream)
 {
     clear_error();
@@ -253,7 +256,17 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
     if (!csr) return fail(PILA_EINVAL, "csr is NULL");
     if (!csr->row_ptr || !csr->trig || !csr->t_row_ptr)
         return fail(PILA_EINVAL, "row_ptr, trig and t_row_ptr must be allocated");
-    hipStream_t st = (hipStream_t)stream;
+    DeviceBuffer tmp;
+    PILA_HIP(hipMalloc(&tmp.p, pila_build_scratch(geom)));
+    return pila_build_with(geom, csr, tmp.p, (hipStream_t)stream);
+}
+
+int32_t pila::pila_build_with(const pila_geom* geom, pila_csr* csr, void* d_scratch, hipStream_t st)
+{
+    PILA_TRY(check_geom(geom));
+    if (!csr || !d_scratch) return fail(PILA_EINVAL, "csr or scratch is NULL");
+    if (!csr->row_ptr || !csr->trig || !csr->t_row_ptr)
+        return fail(PILA_EINVAL, "row_ptr, trig and t_row_ptr must be allocated");
     const int32_t N = geom->n, U = geom->n_angles, K = geom->n_bins;
     const int64_t NP = (int64_t)N * N, G = (int64_t)U * K;
 
@@ -267,14 +280,12 @@ extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream
             rmax2 = std::max(rmax2, xc * xc + yc * yc);
         }
 
-    // temporary device buffer: [0, 256) small results, [256, 256 + N*N) the mask
-    DeviceBuffer tmp;
-    PILA_HIP(hipMalloc(&tmp.p, 256 + (size_t)NP));
-    int64_t* d_small = (int64_t*)tmp.p;
+    // scratch: [0, 256) small results, [256, 256 + N*N) the mask
+    int64_t* d_small = (int64_t*)d_scratch;
     const uint8_t* mk = nullptr;
     if (geom->mask) {
-        PILA_HIP(hipMemcpyAsync((char*)tmp.p + 256, geom->mask, (size_t)NP, hipMemcpyHostToDevice, st));
-        mk = (const uint8_t*)tmp.p + 256;
+        PILA_HIP(hipMemcpyAsync((char*)d_scratch + 256, geom->mask, (size_t)NP, hipMemcpyHostToDevice, st));
+        mk = (const uint8_t*)d_scratch + 256;
     }
 
     if (!csr->col) {  // phase 1: trig, offsets, sizes

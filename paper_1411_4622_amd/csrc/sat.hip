@@ -6,8 +6,148 @@
 #include <vector>
 
 #include "sat_chain.hpp"
+#include "sat_host.hpp"
 
 namespace pila {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t chain_bytes(const pila_geom* g, const sat_params* p)
+{
+    const size_t G = (size_t)g->n_angles * g->n_bins;
+    const size_t T = (G + 63) / 64;
+    const size_t rs = p->precision == PILA_F32 ? 4 : 8;
+    return align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)) +
+           align256(sizeof(sat_stats));
+}
+
+int32_t check_params(const pila_geom* g, const pila_csr* c, const sat_params* p)
+{
+    PILA_TRY(check_geom(g));
+    if (!c || !p) return fail(PILA_EINVAL, "csr or params is NULL");
+    if (!c->row_ptr || !c->col || !c->len || !c->t_row_ptr || !c->t_col || !c->t_len || !c->support)
+        return fail(PILA_EINVAL, "PILA arrays (pixel-major, ray-major and support) are required");
+    if (c->n_support < 1) return fail(PILA_EINVAL, "empty support");
+    if (c->nnz > 0 && (c->max_row < 1 || c->max_row > 2 * g->n_angles))
+        return fail(PILA_EINVAL, "max_row %d is not the longest row from pila_build", c->max_row);
+    if (p->m_cand < 1 || p->m_cand > kMaxCand) return fail(PILA_EINVAL, "m_cand must be in 1..64");
+    if (p->n_steps < 0 || p->n_stages < 1) return fail(PILA_EINVAL, "bad n_steps / n_stages");
+    if (p->precision != PILA_F64 && p->precision != PILA_F32)
+        return fail(PILA_EINVAL, "precision must be PILA_F64 or PILA_F32");
+    if (p->precision != g->len_dtype)
+        return fail(PILA_EINVAL, "the residual precision must match the PILA length type");
+    if (!(p->T0 > 0.0) && (p->q_auto < 1 || !(p->tn_ratio > 0.0)))
+        return fail(PILA_EINVAL, "automatic T0 needs q_auto >= 1 and tn_ratio > 0");
+    if (p->T0 > 0.0 && !(p->TN > 0.0 && std::isfinite(p->T0) && std::isfinite(p->TN)))
+        return fail(PILA_EINVAL, "T0 and TN must be positive and finite");
+    if (!(p->delta_max >= 0.0) || !std::isfinite(p->delta_max) || !(p->f_max >= p->f_min))
+        return fail(PILA_EINVAL, "bad delta_max / value range");
+    if (p->resync_every < 0) return fail(PILA_EINVAL, "resync_every < 0");
+    return PILA_OK;
+}
+
+ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, const sat_params* p,
+                  double* image, char* ws)
+{
+    const size_t G = (size_t)g->n_angles * g->n_bins;
+    const size_t rs = p->precision == PILA_F32 ? 4 : 8;
+    ChainJob J;
+    J.N = g->n;
+    J.U = g->n_angles;
+    J.K = g->n_bins;
+    J.P = c->n_support;
+    J.precision = p->precision;
+    J.m_cand = p->m_cand;
+    J.n_stages = p->n_stages;
+    J.q_auto = p->q_auto;
+    J.n_steps = p->n_steps;
+    J.resync_every = p->precision == PILA_F32 ? p->resync_every : 0;
+    J.seed = p->seed;
+    J.chain_id = p->chain_id;
+    J.T0 = p->T0 > 0.0 ? p->T0 : 0.0;
+    J.TN = p->T0 > 0.0 ? p->TN : 0.0;
+    J.tn_ratio = p->tn_ratio;
+    J.delta_max = p->delta_max;
+    J.f_min = p->f_min;
+    J.f_max = p->f_max;
+    J.ln09 = std::log(0.9);
+    J.row_ptr = c->row_ptr;
+    J.col = c->col;
+    J.len = c->len;
+    J.t_row_ptr = c->t_row_ptr;
+    J.t_col = c->t_col;
+    J.t_len = c->t_len;
+    J.support = c->support;
+    J.sino = sino;
+    J.f = image;
+    J.max_row = c->max_row;
+    J.pad = 0;
+    J.k_lo = c->k_lo;
+    J.Kc = c->k_hi >= c->k_lo ? c->k_hi - c->k_lo + 1 : 0;
+    J.UL = 0;
+    J.pad2 = 0;
+    // g / K for g < 2^24 as (g * m) >> (24 + L), L = ceil(log2 K), m = ceil(2^(24+L) / K):
+    // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K
+    {
+        uint32_t L = 0;
+        while ((1u << L) < (uint32_t)J.K) ++L;
+        const uint64_t den = (uint64_t)1 << (24 + L);
+        J.kdiv_s = 24 + L;
+        J.kdiv_m = (uint32_t)((den + (uint64_t)J.K - 1) / (uint64_t)J.K);
+    }
+    const size_t T = (G + 63) / 64;
+    J.r = ws;
+    J.tsum = (double*)(ws + align256(rs * G));
+    J.tdrift = (double*)(ws + align256(rs * G) + align256(8 * T));
+    J.carry = (ChainCarry*)(ws + align256(rs * G) + 2 * align256(8 * T));
+    J.stats = (sat_stats*)(ws + align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)));
+    J.tr_m = nullptr;
+    J.tr_acc = nullptr;
+    J.tr_dc = nullptr;
+    J.cancel = nullptr;
+    J.cancel_tag = 0;
+    return J;
+}
+
+int device_props(hipDeviceProp_t* prop)
+{
+    int dev = 0;
+    PILA_HIP(hipGetDevice(&dev));
+    PILA_HIP(hipGetDeviceProperties(prop, dev));
+    return PILA_OK;
+}
+
+bool piped_allowed(const pila_geom* g, const pila_csr* c)
+{
+    // ray index g = u K + k below 2^24 (the multiply-shift split), bins
+    // below 8192 (the patch-table tag), and 32-bit byte offsets into the rows
+    const int64_t G = (int64_t)g->n_angles * g->n_bins;
+    const int64_t lb = g->len_dtype == PILA_F32 ? 4 : 8;
+    return c->nnz >= 1 && c->max_row >= 1 && g->n_bins < 8192 && G < (1 << 24) &&
+           c->nnz * lb <= ((int64_t)1 << 32);
+}
+
+// LDS of a pipelined chain whose residual is not wholly in LDS: the patch
+// table, then as many angles of the residual (over the bins the support
+// reaches) as fit in 'budget'.  Sets J->UL; returns the bytes to request.
+int64_t hybrid_lds(ChainJob* J, int64_t budget)
+{
+    const int64_t rs = J->precision == PILA_F32 ? 4 : 8;
+    const int64_t table = (16 * (int64_t)J->U + 2 * rs * J->U + 15) & ~(int64_t)15;
+    J->UL = 0;
+    if (table > budget) return table;
+    if (J->Kc > 0) {
+        const int64_t ul = (budget - table) / (J->Kc * rs);
+        J->UL = (int32_t)std::min<int64_t>(ul, J->U);
+    }
+    return table + (int64_t)J->UL * J->Kc * rs;
+}
+
+int32_t set_lds(const void* k, int bytes)
+{
+    PILA_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return PILA_OK;
+}
 
 namespace {
 
@@ -179,111 +319,6 @@ __global__ void zero_int_kernel(int* p)
     p[1] = 0;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-size_t chain_bytes(const pila_geom* g, const sat_params* p)
-{
-    const size_t G = (size_t)g->n_angles * g->n_bins;
-    const size_t T = (G + 63) / 64;
-    const size_t rs = p->precision == PILA_F32 ? 4 : 8;
-    return align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)) +
-           align256(sizeof(sat_stats));
-}
-
-int32_t check_params(const pila_geom* g, const pila_csr* c, const sat_params* p)
-{
-    PILA_TRY(check_geom(g));
-    if (!c || !p) return fail(PILA_EINVAL, "csr or params is NULL");
-    if (!c->row_ptr || !c->col || !c->len || !c->t_row_ptr || !c->t_col || !c->t_len || !c->support)
-        return fail(PILA_EINVAL, "PILA arrays (pixel-major, ray-major and support) are required");
-    if (c->n_support < 1) return fail(PILA_EINVAL, "empty support");
-    if (c->nnz > 0 && (c->max_row < 1 || c->max_row > 2 * g->n_angles))
-        return fail(PILA_EINVAL, "max_row %d is not the longest row from pila_build", c->max_row);
-    if (p->m_cand < 1 || p->m_cand > kMaxCand) return fail(PILA_EINVAL, "m_cand must be in 1..64");
-    if (p->n_steps < 0 || p->n_stages < 1) return fail(PILA_EINVAL, "bad n_steps / n_stages");
-    if (p->precision != PILA_F64 && p->precision != PILA_F32)
-        return fail(PILA_EINVAL, "precision must be PILA_F64 or PILA_F32");
-    if (p->precision != g->len_dtype)
-        return fail(PILA_EINVAL, "the residual precision must match the PILA length type");
-    if (!(p->T0 > 0.0) && (p->q_auto < 1 || !(p->tn_ratio > 0.0)))
-        return fail(PILA_EINVAL, "automatic T0 needs q_auto >= 1 and tn_ratio > 0");
-    if (p->T0 > 0.0 && !(p->TN > 0.0 && std::isfinite(p->T0) && std::isfinite(p->TN)))
-        return fail(PILA_EINVAL, "T0 and TN must be positive and finite");
-    if (!(p->delta_max >= 0.0) || !std::isfinite(p->delta_max) || !(p->f_max >= p->f_min))
-        return fail(PILA_EINVAL, "bad delta_max / value range");
-    if (p->resync_every < 0) return fail(PILA_EINVAL, "resync_every < 0");
-    return PILA_OK;
-}
-
-ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, const sat_params* p,
-                  double* image, char* ws)
-{
-    const size_t G = (size_t)g->n_angles * g->n_bins;
-    const size_t rs = p->precision == PILA_F32 ? 4 : 8;
-    ChainJob J;
-    J.N = g->n;
-    J.U = g->n_angles;
-    J.K = g->n_bins;
-    J.P = c->n_support;
-    J.precision = p->precision;
-    J.m_cand = p->m_cand;
-    J.n_stages = p->n_stages;
-    J.q_auto = p->q_auto;
-    J.n_steps = p->n_steps;
-    J.resync_every = p->precision == PILA_F32 ? p->resync_every : 0;
-    J.seed = p->seed;
-    J.chain_id = p->chain_id;
-    J.T0 = p->T0 > 0.0 ? p->T0 : 0.0;
-    J.TN = p->T0 > 0.0 ? p->TN : 0.0;
-    J.tn_ratio = p->tn_ratio;
-    J.delta_max = p->delta_max;
-    J.f_min = p->f_min;
-    J.f_max = p->f_max;
-    J.ln09 = std::log(0.9);
-    J.row_ptr = c->row_ptr;
-    J.col = c->col;
-    J.len = c->len;
-    J.t_row_ptr = c->t_row_ptr;
-    J.t_col = c->t_col;
-    J.t_len = c->t_len;
-    J.support = c->support;
-    J.sino = sino;
-    J.f = image;
-    J.max_row = c->max_row;
-    J.pad = 0;
-    J.k_lo = c->k_lo;
-    J.Kc = c->k_hi >= c->k_lo ? c->k_hi - c->k_lo + 1 : 0;
-    J.UL = 0;
-    J.pad2 = 0;
-    // g / K for g < 2^24 as (g * m) >> (24 + L), L = ceil(log2 K), m = ceil(2^(24+L) / K):
-    // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K
-    {
-        uint32_t L = 0;
-        while ((1u << L) < (uint32_t)J.K) ++L;
-        const uint64_t den = (uint64_t)1 << (24 + L);
-        J.kdiv_s = 24 + L;
-        J.kdiv_m = (uint32_t)((den + (uint64_t)J.K - 1) / (uint64_t)J.K);
-    }
-    const size_t T = (G + 63) / 64;
-    J.r = ws;
-    J.tsum = (double*)(ws + align256(rs * G));
-    J.tdrift = (double*)(ws + align256(rs * G) + align256(8 * T));
-    J.carry = (ChainCarry*)(ws + align256(rs * G) + 2 * align256(8 * T));
-    J.stats = (sat_stats*)(ws + align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)));
-    J.tr_m = nullptr;
-    J.tr_acc = nullptr;
-    J.tr_dc = nullptr;
-    return J;
-}
-
-int device_props(hipDeviceProp_t* prop)
-{
-    int dev = 0;
-    PILA_HIP(hipGetDevice(&dev));
-    PILA_HIP(hipGetDeviceProperties(prop, dev));
-    return PILA_OK;
-}
-
 // ---------------------------------------------------------------------------
 // launch tables
 // ---------------------------------------------------------------------------
@@ -311,16 +346,6 @@ const std::vector<PipedShape>& piped_shapes(int precision)
         piped_shape<float, 1, 4>(), piped_shape<float, 1, 8>(), piped_shape<float, 2, 8>(),
         piped_shape<float, 4, 8>()};
     return precision == PILA_F64 ? f64 : f32;
-}
-
-bool piped_allowed(const pila_geom* g, const pila_csr* c)
-{
-    // ray index g = u K + k below 2^24 (the multiply-shift split), bins
-    // below 8192 (the patch-table tag), and 32-bit byte offsets into the rows
-    const int64_t G = (int64_t)g->n_angles * g->n_bins;
-    const int64_t lb = g->len_dtype == PILA_F32 ? 4 : 8;
-    return c->nnz >= 1 && c->max_row >= 1 && g->n_bins < 8192 && G < (1 << 24) &&
-           c->nnz * lb <= ((int64_t)1 << 32);
 }
 
 // Pick the pipelined shape for one chain: the fewest estimates per
@@ -353,28 +378,6 @@ const std::vector<BatchShape>& batch_shapes()
         {1, 4, sat_batch_kernel<1, 4>}, {1, 8, sat_batch_kernel<1, 8>}, {2, 8, sat_batch_kernel<2, 8>},
         {4, 8, sat_batch_kernel<4, 8>}};
     return v;
-}
-
-// LDS of a pipelined chain whose residual is not wholly in LDS: the patch
-// table, then as many angles of the residual (over the bins the support
-// reaches) as fit in 'budget'.  Sets J->UL; returns the bytes to request.
-int64_t hybrid_lds(ChainJob* J, int64_t budget)
-{
-    const int64_t rs = J->precision == PILA_F32 ? 4 : 8;
-    const int64_t table = (16 * (int64_t)J->U + 2 * rs * J->U + 15) & ~(int64_t)15;
-    J->UL = 0;
-    if (table > budget) return table;
-    if (J->Kc > 0) {
-        const int64_t ul = (budget - table) / (J->Kc * rs);
-        J->UL = (int32_t)std::min<int64_t>(ul, J->U);
-    }
-    return table + (int64_t)J->UL * J->Kc * rs;
-}
-
-int32_t set_lds(const void* k, int bytes)
-{
-    PILA_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    return PILA_OK;
 }
 
 // HIP events around each chain-kernel launch of one sat_run, summed after

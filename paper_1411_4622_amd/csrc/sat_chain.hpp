@@ -76,6 +76,8 @@ struct ChainJob {
     int32_t* tr_m;
     uint8_t* tr_acc;
     double* tr_dc;
+    const uint64_t* cancel;  // served chains: host word that equals cancel_tag once cancelled
+    uint64_t cancel_tag;
 };
 
 constexpr int kMaxCand = 64;
@@ -91,7 +93,64 @@ struct ChainShared {
     double fnstar;
     int32_t pstar;
     int32_t ticket;
+    int32_t stop;
 };
+
+// A copy of a descriptor held in LDS whose every field the compiler knows to
+// be the same in all lanes (so it lives in scalar registers, as a kernel
+// argument would).
+template <typename T>
+__device__ __forceinline__ T lane0(T x)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit fields");
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u;
+        __builtin_memcpy(&u, &x, 4);
+        u = __builtin_amdgcn_readfirstlane(u);
+        __builtin_memcpy(&x, &u, 4);
+    } else {
+        uint64_t u;
+        __builtin_memcpy(&u, &x, 8);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+        u = ((uint64_t)hi << 32) | lo;
+        __builtin_memcpy(&x, &u, 8);
+    }
+    return x;
+}
+
+__device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
+{
+    ChainJob J;
+#define PILA_F(f) J.f = lane0(d.f);
+    PILA_F(N) PILA_F(U) PILA_F(K) PILA_F(P) PILA_F(precision) PILA_F(m_cand) PILA_F(n_stages)
+    PILA_F(q_auto) PILA_F(max_row) PILA_F(pad) PILA_F(k_lo) PILA_F(Kc) PILA_F(UL) PILA_F(pad2)
+    PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
+    PILA_F(T0) PILA_F(TN) PILA_F(tn_ratio) PILA_F(delta_max) PILA_F(f_min) PILA_F(f_max) PILA_F(ln09)
+    PILA_F(row_ptr) PILA_F(col) PILA_F(len) PILA_F(t_row_ptr) PILA_F(t_col) PILA_F(t_len)
+    PILA_F(support) PILA_F(sino) PILA_F(f) PILA_F(r) PILA_F(tsum) PILA_F(tdrift) PILA_F(carry)
+    PILA_F(stats) PILA_F(tr_m) PILA_F(tr_acc) PILA_F(tr_dc) PILA_F(cancel) PILA_F(cancel_tag)
+#undef PILA_F
+    return J;
+}
+
+// Cancellation of a served chain: thread 0 reads the host word every
+// kCancelEvery steps before a barrier, every thread reads its copy after a
+// later barrier of the same step, so the whole workgroup leaves together.
+// The read is an acquire at system scope: its cache invalidation makes the
+// next read fetch the word from host memory again, so a cancellation is seen
+// within two checks.
+constexpr int64_t kCancelEvery = 1024;
+
+__device__ __forceinline__ void cancel_probe(const ChainJob& J, ChainShared& sh, int64_t s)
+{
+    if (J.cancel && (s & (kCancelEvery - 1)) == 0 && threadIdx.x == 0)
+        sh.stop = __hip_atomic_load(J.cancel, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == J.cancel_tag;
+}
+__device__ __forceinline__ bool cancel_seen(const ChainJob& J, const ChainShared& sh, int64_t s)
+{
+    return J.cancel && (s & (kCancelEvery - 1)) == 0 && sh.stop;
+}
 
 // pipelined workgroups hold at most 8 wavefronts (up to 256 registers per lane)
 constexpr int kPipedThreads = 512;
@@ -588,6 +647,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
         const double co = sqrt(cs.sse / KU);
         const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
         const double lnN1 = log(N1), invT = 1.0 / T;
+        cancel_probe(J, sh, s);
         __syncthreads();
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, N1, lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
@@ -606,6 +666,11 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
         if (f32 && J.resync_every > 0 && cs.since >= J.resync_every)
             resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
         __syncthreads();
+        if (cancel_seen(J, sh, s)) {
+            cs.status = PILA_ECANCELED;
+            cs.n_steps = s + 1;
+            break;
+        }
     }
     write_stats(J, cs);
 }
@@ -670,7 +735,7 @@ __device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
     }
 }
 
-template <typename Real, bool RLDS, int CPW, int E>
+template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false>
 __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int LPC = kWave / CPW;  // lanes per estimate
@@ -715,7 +780,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         D.lnN1 = 0.0;
         // the key is made opaque here, so that the round keys are formed per
         // block instead of being held in scalar registers across the loop
-        uint64_t k0 = J.seed, k1 = J.chain_id;
+        uint64_t k0 = lane0(J.seed), k1 = lane0(J.chain_id);
         asm volatile("" : "+s"(k0), "+s"(k1));
         if (s < n_steps) {
             if (m < M) {
@@ -809,7 +874,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     // One step with X the estimates of step s, Y those of s + 1 (their
     // global operands are loaded here) and Z those of s + 2 (rows loaded
     // here).  The loop below rotates the roles, so no registers are copied.
-    // Returns true when a segmented chain must stop for a resync.
+    // Returns true when the chain stops here: a segmented chain for a
+    // resync, or a served chain that has been cancelled (then cancelled is set).
+    bool cancelled = false;
     auto step = [&](RowSet<Real, E>& X, RowSet<Real, E>& Y, RowSet<Real, E>& Z, int64_t s)
                     __attribute__((always_inline)) -> bool {
         const double T = sched.at(s, n_steps, J.n_stages);
@@ -856,6 +923,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         Y.fo = J.f[Y.p];
         prefetch(Z, s + 2);
         const double co = sqrt(cs.sse / KU);
+        if (SERVED) cancel_probe(J, sh, s);
         __syncthreads();
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, X.N1, X.lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
@@ -924,15 +992,30 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             else if (RLDS)
                 Y.rv[e] = rget(Y.col[e]);
         }
+        if (SERVED && cancel_seen(J, sh, s)) {
+            cs.status = PILA_ECANCELED;
+            cs.n_steps = s + 1;
+            cancelled = true;
+            return true;
+        }
         return false;
     };
 
     for (int64_t s = s_begin; s < n_steps;) {
-        if (step(A, B, C, s)) return;
+        if (step(A, B, C, s)) {
+            if (SERVED && cancelled) break;
+            return;
+        }
         if (++s >= n_steps) break;
-        if (step(B, C, A, s)) return;
+        if (step(B, C, A, s)) {
+            if (SERVED && cancelled) break;
+            return;
+        }
         if (++s >= n_steps) break;
-        if (step(C, A, B, s)) return;
+        if (step(C, A, B, s)) {
+            if (SERVED && cancelled) break;
+            return;
+        }
         ++s;
     }
     if (!RLDS) {

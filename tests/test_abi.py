@@ -125,6 +125,26 @@ def test_batch_argument_errors(P):
     assert lib.sat_run_batch(0, None, None, None, 0, None, None) == P._binding.PILA_ENOMEM
 
 
+def test_server_argument_errors(P):
+    from paper_1411_4622_amd._binding import CSrvConfig, CSrvStatus
+    lib = P.load()
+    h = C.c_void_p()
+    E = P._binding.PILA_EINVAL
+    assert lib.srv_create(None, C.byref(h)) == E
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 5, 0, 0)), C.byref(h)) == E
+    assert "waves_per_chain" in P.last_error()
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 8, 3, 0)), C.byref(h)) == E
+    assert "power of two" in P.last_error()
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 10, 0, 8, 0, 0)), C.byref(h)) == P._binding.PILA_ENOMEM
+    done = C.c_int32(0)
+    assert lib.srv_poll(None, 0, C.byref(done), None) == E
+    assert lib.srv_cancel(None, 0) == E
+    assert lib.srv_get_status(None, C.byref(CSrvStatus())) == E
+    assert lib.srv_submit(None, None, None) == E
+    assert lib.srv_prepare(None, None) == E
+    assert lib.srv_destroy(None) == 0
+
+
 def test_product_path_does_not_import_oracle():
     pkg = os.path.join(ROOT, "paper_1411_4622_amd")
     for dirpath, _, files in os.walk(pkg):
