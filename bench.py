@@ -111,6 +111,19 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (counter "
                          "calibration for rocprofv3 --pmc runs)")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
+                    help="c2 (default): the single-chain benchmark line; c3: batch of slices; "
+                         "c4: 1024^2 slice, SAT M=32 and SIRT; c5: serving stream")
+    ap.add_argument("--slices", type=int, default=512, help="c3: slices in the batch")
+    ap.add_argument("--distinct", type=int, default=64,
+                    help="c3: distinct phantoms generated (the rest repeat them with other seeds)")
+    ap.add_argument("--requests", type=int, default=2000, help="c5: requests in the stream")
+    ap.add_argument("--rate", type=float, default=200.0, help="c5: arrivals per second")
+    ap.add_argument("--sweeps", type=float, default=None, help="c3/c5: steps = sweeps x support")
+    ap.add_argument("--sat-steps", type=int, default=None, help="c4: chain steps")
+    ap.add_argument("--mem-budget-gb", type=float, default=96.0, help="c5: server memory budget")
+    ap.add_argument("--general-slots", type=int, default=96,
+                    help="c5: server slots for the general body (long rows)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,6 +131,9 @@ def main() -> int:
         print("bench.py runs on one GPU: an annealing chain does not shard across GPUs, and this "
               "build measures the one-GPU path only (--gpus 1).", file=sys.stderr)
         return 2
+    if args.workload != "c2":
+        import bench_workloads
+        return bench_workloads.run(args)
 
     import torch
     import datagen

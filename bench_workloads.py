@@ -1,0 +1,374 @@
+"""Workloads beside the single-chain benchmark line (bench.py --workload ...).
+
+c3  batch: slices cut from one seeded ellipsoid volume (N in {128, 256, 512},
+    90/180/360 angles, K = ceil(sqrt(2) N), Poisson noise I0 = 1e4, circular
+    support), M = 8, FP32 residual with FP64 resync every 4096 accepted
+    nonzero changes, 16 sweeps of the support, all chains in one persistent
+    launch whose shape the tuner picks.  --distinct phantoms are generated and
+    repeated with other chain seeds up to --slices chains.
+c4  one 1024 x 1024 slice (30 ellipses, 720 angles, 1449 bins, I0 = 1e4,
+    circular support): the PILA build, a SAT chain at M = 32 (FP32 residual,
+    FP64 resync) and 200 SIRT iterations (relaxation 0.1).
+c5  serving: requests arrive by a Poisson process; each is a slice with N in
+    {128, 256, 384, 512, 768, 1024}, 90/180/360/720 angles and an ellipse
+    phantom with Poisson noise at I0 drawn in [1e3, 1e5]; the server admits
+    them against its memory budget and runs them as workgroups free up.
+
+Every input is synthetic and seeded.  Each workload prints one JSON line.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import statistics
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _pool_map(fn, items, procs=16):
+    procs = max(1, min(procs, len(items), os.cpu_count() or 1))
+    if procs == 1:
+        return [fn(x) for x in items]
+    with ProcessPoolExecutor(max_workers=procs) as ex:
+        return list(ex.map(fn, items, chunksize=1))
+
+
+def resync_interval(cfg, nnz):
+    """Accepted nonzero changes between FP64 resyncs for the batch and serving
+    workloads, which do not fix it: at least the configured 4096, and at
+    least nnz / 4096, so that the full-PILA rebuild (16 bytes per entry)
+    stays a small share of the chain's own traffic on large slices."""
+    return max(int(cfg["resync_every"]), int(nnz) // 4096)
+
+
+def _params(P, cfg, n_steps, seed, chain_id, precision="f32", nnz=0):
+    return P.SatParams(n_steps=int(n_steps), seed=seed, chain_id=chain_id, n_stages=cfg["n_stages"],
+                       m_cand=cfg["M"], T0=None, q_auto=cfg["q_auto"], precision=precision,
+                       tn_ratio=cfg["tn_ratio"], delta_max=cfg["delta_max"], f_min=cfg["f_min"],
+                       f_max=cfg["f_max"],
+                       resync_every=resync_interval(cfg, nnz) if precision == "f32" else 0)
+
+
+def _chain_bytes(n_steps, M, f_mean, accepts):
+    # the single-chain kernel's per-estimate and per-accept bytes (FP32)
+    return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
+
+
+# ---------------------------------------------------------------------------
+# c3: batch
+# ---------------------------------------------------------------------------
+
+def run_c3(args, P, torch, datagen):
+    from paper_1411_4622_amd.tune import tune_batch
+    cfg = datagen.CONFIGS["c3"]
+    sweeps = args.sweeps if args.sweeps is not None else cfg["sweeps"]
+    n_dist = min(args.distinct, args.slices)
+    specs = datagen.batch_slice_specs(cfg["volume_seed"], n_dist, cfg["sizes"], cfg["n_angles"],
+                                      cfg["I0"], cfg["masked"])
+    t0 = time.perf_counter()
+    slices = _pool_map(datagen.slice_from_spec, specs)
+    log("c3: %d distinct slices generated in %.1f s" % (len(slices), time.perf_counter() - t0))
+    geoms, pilas = {}, {}
+    for sl in slices:
+        key = (sl.N, sl.U)
+        if key not in pilas:
+            g = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+            geoms[key], pilas[key] = g, P.pila_build(g)
+    dev = torch.device("cuda", 0)
+    sinos = [torch.from_numpy(sl.sino).to(dev) for sl in slices]
+    jobs = []
+    for c in range(args.slices):
+        sl = slices[c % n_dist]
+        P_sup = int(sl.mask.sum())
+        pl = pilas[(sl.N, sl.U)]
+        prm = _params(P, cfg, round(sweeps * P_sup), cfg["chain_seed0"] + c, c, nnz=pl.nnz)
+        jobs.append(P.Job(pl, sinos[c % n_dist],
+                          torch.from_numpy(sl.f0.copy()).to(dev), prm))
+    f0s = [j.image.clone() for j in jobs]
+    (waves, per_cu), table = tune_batch(jobs, sample_steps=4096)
+    log("c3: tuned launch shape %d waves/chain, %d chains/CU: %s"
+        % (waves, per_cu, ", ".join("(%d,%d) %.3g/s" % (r["waves_per_chain"], r["chains_per_cu"],
+                                                          r["proposals_per_s"]) for r in table)))
+    for j, f in zip(jobs, f0s):
+        j.image.copy_(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = P.sat_run_batch(jobs, waves_per_chain=waves, chains_per_cu=per_cu)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = sum(j.params.n_steps for j in jobs)
+    M = cfg["M"]
+    rm32 = [datagen.rmse(j.image.cpu().numpy(), slices[c % n_dist].truth) for c, j in enumerate(jobs)]
+    drift = max(s["max_drift_r"] for s in stats)
+    # FP64 chains with the same seeds on a sample of slices, for the RMSE ratio
+    sample = list(range(0, len(jobs), max(1, len(jobs) // 8)))[:8]
+    jobs64, keys64 = [], []
+    for c in sample:
+        sl = slices[c % n_dist]
+        g64 = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f64")
+        key = (sl.N, sl.U)
+        if key not in keys64:
+            keys64.append(key)
+        pl64 = P.pila_build(g64)
+        prm = _params(P, cfg, jobs[c].params.n_steps, cfg["chain_seed0"] + c, c, "f64")
+        jobs64.append(P.Job(pl64, sinos[c % n_dist], f0s[c].clone(), prm))
+    log("c3: %d FP64 reference chains" % len(jobs64))
+    P.sat_run_batch(jobs64, waves_per_chain=8, chains_per_cu=1)
+    torch.cuda.synchronize()
+    ratios = []
+    for c, j64 in zip(sample, jobs64):
+        r64 = datagen.rmse(j64.image.cpu().numpy(), slices[c % n_dist].truth)
+        ratios.append(rm32[c] / r64 if r64 > 0 else float("nan"))
+    # the plain one-chain GPU form at the same M on the most common geometry
+    common = max(pilas, key=lambda k: sum(1 for c in range(len(jobs))
+                                          if (slices[c % n_dist].N, slices[c % n_dist].U) == k))
+    c0 = next(c for c in range(len(jobs)) if (slices[c % n_dist].N, slices[c % n_dist].U) == common)
+    single_steps = min(jobs[c0].params.n_steps, 200_000)
+    img = f0s[c0].clone()
+    prm1 = _params(P, cfg, single_steps, cfg["chain_seed0"] + c0, c0, nnz=pilas[common].nnz)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.sat_run(pilas[common], sinos[c0 % n_dist], prm1, img)
+    e1.record()
+    e1.synchronize()
+    single_rate = single_steps * M / (e0.elapsed_time(e1) / 1e3)
+    f_mean = statistics.mean(pl.nnz / pl.n_support for pl in pilas.values())
+    alg = sum(_chain_bytes(j.params.n_steps, M, j.pila.nnz / j.pila.n_support, s["accepts"])
+              for j, s in zip(jobs, stats))
+    out = {
+        "workload": "c3",
+        "metric": "SA proposals evaluated/s + slices/s (batch of independent slices)",
+        "value": steps * M / wall, "unit": "proposals/s",
+        "slices": len(jobs), "distinct_phantoms": n_dist, "sweeps": sweeps, "M": M,
+        "steps_total": steps, "wall_s": wall, "slices_per_s": len(jobs) / wall,
+        "launch_shape": {"waves_per_chain": waves, "chains_per_cu": per_cu, "tuner": table},
+        "single_chain_proposals_per_s": single_rate,
+        "single_chain_geometry": {"N": common[0], "U": common[1]},
+        "batch_over_single": steps * M / wall / single_rate,
+        "rmse_fp32_mean": statistics.mean(rm32),
+        "rmse_ratio_fp32_fp64_sample": ratios, "max_drift_r": drift,
+        "roofline": {"kernel": "sat_batch_kernel", "bound": "hbm",
+                     "achieved": alg / wall / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / wall / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg,
+                     "mean_row": f_mean},
+        "data": "synthetic: slices of a seeded 32-ellipsoid volume, analytic line integrals, "
+                "Poisson noise I0=1e4",
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# c4: large slice, SAT M=32 and SIRT
+# ---------------------------------------------------------------------------
+
+def run_c4(args, P, torch, datagen):
+    cfg = datagen.CONFIGS["c4"]
+    t0 = time.perf_counter()
+    sl = datagen.config_slice("c4")
+    log("c4: slice generated in %.1f s" % (time.perf_counter() - t0))
+    dev = torch.device("cuda", 0)
+    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl = P.pila_build(geom)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log("c4: PILA nnz %d (%.2f GB per order) built in %.2f s" % (pl.nnz, pl.nnz * 8 / 1e9, build_s))
+    sino = torch.from_numpy(sl.sino).to(dev)
+    f0 = torch.from_numpy(sl.f0).to(dev)
+    # SIRT
+    n_it, lam = cfg["sirt_iters"], cfg["sirt_lambda"]
+    img = f0.clone()
+    P.sirt_run(pl, sino, 2, lam, img, cost=False)  # warm-up
+    img.copy_(f0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    costs = P.sirt_run(pl, sino, n_it, lam, img, cost=False)
+    e1.record()
+    e1.synchronize()
+    sirt_s = e0.elapsed_time(e1) / 1e3
+    rm_sirt = datagen.rmse(img.cpu().numpy(), sl.truth)
+    G = sl.U * sl.K
+    NP = sl.N * sl.N
+    # per iteration: both PILA orders (ray or pixel index 4 + length 4 per entry),
+    # both offset arrays, image read twice and written once, residual written and read
+    sirt_bytes = n_it * (2 * 8.0 * pl.nnz + 8.0 * (G + NP) + 3 * 8.0 * NP + 2 * 8.0 * G)
+    log("c4: SIRT %d iterations in %.3f s (%.1f GB/s algorithmic)"
+        % (n_it, sirt_s, sirt_bytes / sirt_s / 1e9))
+    # SAT chain
+    steps = args.sat_steps or cfg["n_steps"]
+    prm = _params(P, cfg, steps, cfg["chain_seed"], 0)  # c4 keeps resync every 4096
+    img.copy_(f0)
+    e0.record()
+    st, _ = P.sat_run(pl, sino, prm, img)
+    e1.record()
+    e1.synchronize()
+    sat_s = e0.elapsed_time(e1) / 1e3
+    rm_sat = datagen.rmse(img.cpu().numpy(), sl.truth)
+    out = {
+        "workload": "c4", "N": sl.N, "U": sl.U, "K": sl.K, "nnz": pl.nnz, "max_row": pl.max_row,
+        "pila_build_s": build_s,
+        "sirt": {"iterations": n_it, "lambda": lam, "seconds": sirt_s, "ms_per_iteration":
+                 1e3 * sirt_s / n_it, "rmse": rm_sirt,
+                 "roofline": {"kernel": "ray_gather_kernel + pixel_gather_kernel", "bound": "hbm",
+                              "achieved": sirt_bytes / sirt_s / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": sirt_bytes / sirt_s / 1e9 / HBM_PEAK_GBS,
+                              "algorithmic_bytes": sirt_bytes}},
+        "sat": {"steps": steps, "M": cfg["M"], "seconds": sat_s,
+                "proposals_per_s": steps * cfg["M"] / sat_s, "us_per_step": 1e6 * sat_s / steps,
+                "accepts": st["accepts"], "resyncs": st["resyncs"], "max_drift_r": st["max_drift_r"],
+                "rmse": rm_sat},
+        "data": "synthetic: seeded 30-ellipse phantom, analytic line integrals, Poisson noise I0=1e4",
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# c5: serving stream
+# ---------------------------------------------------------------------------
+
+def _c5_pool_item(arg):
+    import datagen
+    N, U, ph, seed = arg
+    ell = datagen.random_ellipses(seed, N, 10)
+    K = datagen.n_bins_for(N)
+    sino = datagen.radon_ellipses(ell, N, datagen.angles_deg(U), K)
+    truth = datagen.rasterize(ell, N)
+    return (N, U, ph, sino, truth)
+
+
+def run_c5(args, P, torch, datagen):
+    cfg = datagen.CONFIGS["c5"]
+    sweeps = args.sweeps if args.sweeps is not None else 1.0
+    rng = np.random.default_rng(cfg["seed"])
+    n_req = args.requests
+    sizes, angs = cfg["sizes"], cfg["n_angles"]
+    n_ph = 2  # phantoms per geometry in the pool
+    items = [(N, U, ph, cfg["seed"] * 100000 + N * 1000 + U * 3 + ph) for N in sizes for U in angs
+             for ph in range(n_ph)]
+    t0 = time.perf_counter()
+    pool = _pool_map(_c5_pool_item, items)
+    log("c5: %d clean sinograms generated in %.1f s" % (len(pool), time.perf_counter() - t0))
+    clean = {(N, U, ph): (sino, truth) for N, U, ph, sino, truth in pool}
+    masks = {N: datagen.circle_mask(N) for N in sizes}
+    geoms = {(N, U): P.Geometry(N, datagen.angles_deg(U), datagen.n_bins_for(N), masks[N], "f32")
+             for N in sizes for U in angs}
+    # requests: arrival time, geometry, phantom, I0, noise seed
+    gaps = rng.exponential(1.0 / args.rate, size=n_req)
+    arrive = np.cumsum(gaps)
+    reqs = []
+    for i in range(n_req):
+        N = int(rng.choice(sizes))
+        U = int(rng.choice(angs))
+        ph = int(rng.integers(n_ph))
+        I0 = float(rng.uniform(*cfg["I0_range"]))
+        reqs.append((float(arrive[i]), N, U, ph, I0, cfg["seed"] * 1000003 + i))
+    # noisy sinograms: a few noise levels per (geometry, phantom) reused across requests
+    dev = torch.device("cuda", 0)
+    noisy = {}
+    levels = np.geomspace(cfg["I0_range"][0], cfg["I0_range"][1], 4)
+    for (N, U, ph), (sino, _) in clean.items():
+        for li, I0 in enumerate(levels):
+            s = datagen.poisson_noise(sino, N, float(I0), cfg["seed"] + 7919 * li + N + U + ph)
+            f0 = datagen.uniform_start(s, masks[N], N, cfg["f_min"], cfg["f_max"])
+            noisy[(N, U, ph, li)] = (torch.from_numpy(s).to(dev), torch.from_numpy(f0).to(dev))
+    log("c5: %d noisy sinograms on the device" % len(noisy))
+
+    budget = int(args.mem_budget_gb * (1 << 30))
+    srv = P.Server(mem_budget=budget, idle_us=20000, general_slots=args.general_slots)
+    t0 = time.perf_counter()
+    for g in geoms.values():
+        srv.prepare(g)
+    prep_s = time.perf_counter() - t0
+    st0 = srv.status()
+    log("c5: %d PILAs prepared in %.1f s (%.1f GB)" % (st0["pila_cached"], prep_s, st0["bytes_used"] / 1e9))
+
+    torch.cuda.current_stream().synchronize()
+    lat, done_at, steps_done, props, rm = [], [], 0, 0, []
+    waiting = []  # arrived, not yet admitted
+    inflight = {}
+    nxt = 0
+    busy_retries = 0
+    start = time.perf_counter()
+    last_log = start
+    while nxt < n_req or waiting or inflight:
+        now = time.perf_counter() - start
+        while nxt < n_req and reqs[nxt][0] <= now:
+            waiting.append(reqs[nxt])
+            nxt += 1
+        while waiting:
+            a, N, U, ph, I0, seed = waiting[0]
+            li = int(np.argmin(np.abs(np.log(levels) - math.log(I0))))
+            sino, f0 = noisy[(N, U, ph, li)]
+            img = f0.clone()
+            torch.cuda.current_stream().synchronize()
+            P_sup = int(masks[N].sum())
+            prm = _params(P, cfg, max(1, round(sweeps * P_sup)), seed, 0,
+                          nnz=int(P_sup * U * 4 / math.pi))
+            t = srv.submit(geoms[(N, U)], sino, img, prm)
+            if t is None:
+                busy_retries += 1
+                break
+            waiting.pop(0)
+            inflight[t] = (a, N, U, ph, img, prm.n_steps)
+        for t in list(inflight):
+            st = srv.poll(t)
+            if st is None:
+                continue
+            a, N, U, ph, img, n_steps = inflight.pop(t)
+            fin = time.perf_counter() - start
+            lat.append(fin - a)
+            done_at.append(fin)
+            steps_done += n_steps
+            props += n_steps * cfg["M"]
+            if len(rm) < 200:
+                rm.append((N, datagen.rmse(img.cpu().numpy(), clean[(N, U, ph)][1])))
+        if time.perf_counter() - last_log > 5:
+            last_log = time.perf_counter()
+            log("c5: t=%.1f s arrived %d done %d in flight %d waiting %d"
+                % (now, nxt, len(lat), len(inflight), len(waiting)))
+        time.sleep(0.0005)
+    span = max(done_at) - reqs[0][0]
+    stat = srv.status()
+    srv.close()
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "workload": "c5",
+        "metric": "slices/s and p50/p99 latency of a Poisson request stream (continuous batching)",
+        "requests": n_req, "rate_per_s": args.rate, "sweeps": sweeps, "M": cfg["M"],
+        "slices_per_s": n_req / span, "proposals_per_s": props / span, "steps_per_s": steps_done / span,
+        "latency_ms_p50": float(np.percentile(lat_ms, 50)),
+        "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+        "latency_ms_mean": float(lat_ms.mean()),
+        "span_s": span, "pila_prepare_s": prep_s, "busy_retries": busy_retries,
+        "kernel_launches": stat["launches"], "bytes_used_peak_after_prepare": st0["bytes_used"],
+        "rmse_by_N_sample": {str(N): float(np.mean([r for n, r in rm if n == N]))
+                             for N in sorted({n for n, _ in rm})},
+        "data": "synthetic: seeded 10-ellipse phantoms (2 per geometry), analytic line integrals, "
+                "Poisson noise at 4 levels in [1e3, 1e5] (each request takes the level nearest "
+                "its drawn I0)",
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run(args) -> int:
+    import torch
+    import datagen
+    import paper_1411_4622_amd as P
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    return {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args, P, torch, datagen)

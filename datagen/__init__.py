@@ -332,9 +332,11 @@ def config_slice(name: str) -> Slice:
                       noise_seed=c.get("noise_seed", 0), f_min=c["f_min"], f_max=c["f_max"])
 
 
-def batch_slices(seed: int, n: int, sizes, n_angles, I0: float, masked: bool = True,
-                 volume_seed: Optional[int] = None) -> List[Slice]:
-    """n slices cut from one random ellipsoid volume, sizes drawn per slice."""
+def batch_slice_specs(seed: int, n: int, sizes, n_angles, I0: float, masked: bool = True,
+                      volume_seed: Optional[int] = None) -> List[dict]:
+    """Arguments of make_slice for n slices cut from one random ellipsoid volume
+    (sizes and angle counts drawn per slice), so that callers may build the
+    slices in parallel; batch_slices builds them in order."""
     rng = np.random.default_rng(seed)
     vol = random_ellipsoids(seed if volume_seed is None else volume_seed)
     out = []
@@ -342,7 +344,18 @@ def batch_slices(seed: int, n: int, sizes, n_angles, I0: float, masked: bool = T
         z = -0.9 + 1.8 * s / max(n - 1, 1)
         N = int(rng.choice(sizes))
         U = int(rng.choice(n_angles))
-        K = n_bins_for(N)
-        ell = volume_slice(vol, z, N)
-        out.append(make_slice(N, U, K, ell, masked=masked, I0=I0, noise_seed=seed * 1000 + s))
+        out.append(dict(N=N, U=U, K=n_bins_for(N), ell=volume_slice(vol, z, N), masked=masked,
+                        I0=I0, noise_seed=seed * 1000 + s))
     return out
+
+
+def slice_from_spec(spec: dict) -> Slice:
+    return make_slice(spec["N"], spec["U"], spec["K"], spec["ell"], masked=spec["masked"],
+                      I0=spec["I0"], noise_seed=spec["noise_seed"])
+
+
+def batch_slices(seed: int, n: int, sizes, n_angles, I0: float, masked: bool = True,
+                 volume_seed: Optional[int] = None) -> List[Slice]:
+    """n slices cut from one random ellipsoid volume, sizes drawn per slice."""
+    return [slice_from_spec(sp) for sp in batch_slice_specs(seed, n, sizes, n_angles, I0, masked,
+                                                            volume_seed)]

@@ -276,6 +276,9 @@ typedef struct srv_config {
     int32_t ring_size;       /* tickets submitted and not yet reaped; power of two, 0 = 1024 */
     int32_t idle_us;         /* a workgroup that finds no work for this long exits; the
                                 server relaunches on the next submission (0 = 20000) */
+    int32_t general_slots;   /* of max_slots, those that run the general body (chains the
+                                pipelined body does not take: FP64, long rows, large M);
+                                0 = max_slots / 8 */
 } srv_config;
 
 typedef struct srv_request {

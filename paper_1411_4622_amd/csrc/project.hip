@@ -23,6 +23,39 @@ constexpr int kWPB = 4;              // wavefronts per block
 
 enum { kFwd = 0, kResW = 1, kW = 2 };
 
+// This lane's share of one CSR row's dot product with a gathered vector x
+// (or, SQUARES, of the row's squared lengths): entries q = b + lane + 64 i in
+// ascending i, fused multiply-add in FP64.  kU entries are loaded before any
+// is used, so each lane keeps kU row loads and kU gathers in flight.
+constexpr int kU = 8;
+
+template <typename LenT, bool SQUARES>
+__device__ __forceinline__ double row_dot(int64_t b, int64_t e, int lane,
+                                          const int32_t* __restrict__ ci,
+                                          const LenT* __restrict__ ln,
+                                          const double* __restrict__ x)
+{
+    double acc = 0.0;
+    for (int64_t q0 = b + lane; q0 < e; q0 += 64 * kU) {
+        double l[kU], v[kU];
+        int32_t c[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t q = q0 + 64 * u < e ? q0 + 64 * u : b;
+            l[u] = (double)ln[q];
+            if (!SQUARES) c[u] = ci[q];
+        }
+        if (!SQUARES) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v[u] = x[c[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (q0 + 64 * u < e) acc = fma(l[u], SQUARES ? l[u] : v[u], acc);
+    }
+    return acc;
+}
+
 template <typename LenT, int MODE>
 __global__ __launch_bounds__(256) void ray_gather_kernel(int64_t G, const int64_t* __restrict__ rp,
                                                          const int32_t* __restrict__ ci,
@@ -38,15 +71,7 @@ __global__ __launch_bounds__(256) void ray_gather_kernel(int64_t G, const int64_
     double sq = 0.0;  // lane 0: this wavefront's sum of squared residuals
     for (int64_t g = (int64_t)blockIdx.x * kWPB + w; g < G; g += (int64_t)gridDim.x * kWPB) {
         const int64_t b = rp[g], e = rp[g + 1];
-        double acc = 0.0;
-        for (int64_t q = b + lane; q < e; q += 64) {
-            const double l = (double)ln[q];
-            if (MODE == kW)
-                acc = fma(l, l, acc);
-            else
-                acc = fma(l, f[ci[q]], acc);
-        }
-        acc = wave_sum(acc);
+        const double acc = wave_sum(row_dot<LenT, MODE == kW>(b, e, lane, ci, ln, f));
         if (lane == 0) {
             if (MODE == kResW) {
                 const double res = sino[g] - acc;
@@ -95,9 +120,7 @@ __global__ __launch_bounds__(256) void pixel_gather_kernel(int64_t NP, const int
     for (int64_t p = (int64_t)blockIdx.x * kWPB + w; p < NP; p += (int64_t)gridDim.x * kWPB) {
         const int64_t b = rp[p], e = rp[p + 1];
         if (MODE == kSirt && b == e) continue;
-        double acc = 0.0;
-        for (int64_t q = b + lane; q < e; q += 64) acc = fma((double)ln[q], y[ci[q]], acc);
-        acc = wave_sum(acc);
+        const double acc = wave_sum(row_dot<LenT, false>(b, e, lane, ci, ln, y));
         if (lane == 0) {
             if (MODE == kSirt)
                 out[p] = out[p] + scale * acc;

@@ -170,6 +170,16 @@ __global__ __launch_bounds__(kPipedThreads) void sat_segment_kernel(ChainJob job
     run_chain_piped<float, false, CPW, E>(job, lds, sh, true);
 }
 
+// one segment of a general-body chain (FP32, residual in global memory)
+// whose FP64 resyncs run grid-wide between segments
+__global__ __launch_bounds__(1024) void sat_simple_segment_kernel(ChainJob job)
+{
+    extern __shared__ __align__(16) char lds[];
+    __shared__ ChainShared sh;
+    if (job.carry->done || job.carry->status != PILA_OK) return;
+    run_chain_simple<float, false>(job, lds, sh, true);
+}
+
 // one chain, general body
 template <typename Real>
 __global__ __launch_bounds__(1024) void sat_simple_kernel(ChainJob job, int lds_bytes)
@@ -467,7 +477,9 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         piped_allowed(geom, csr) ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
                                  : nullptr;
     const bool resync = params->precision == PILA_F32 && params->resync_every > 0;
-    if (ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg) {
+    const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
+    const bool simple_seg = !ps && !r_in_lds && resync;
+    if (piped_seg || simple_seg) {
         // FP32 residual in global memory: chain segments end at each resync,
         // which runs grid-wide; the host only enqueues, it never waits
         const int T = (int)((G + 63) / 64);
@@ -475,8 +487,15 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 0);
         sat_setup_kernel<float><<<1, kPipedThreads, 0, st>>>(J);
         const int64_t n_seg = params->n_steps / params->resync_every + 1;
+        const int sw = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         for (int64_t k = 0; k < n_seg; ++k) {
-            PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
+            if (piped_seg) {
+                PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
+            } else {
+                PILA_TRY(tm.mark(st));
+                sat_simple_segment_kernel<<<1, sw * kWave, 0, st>>>(J);
+                PILA_TRY(tm.mark(st));
+            }
             sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 1);
             sat_resync_finish_kernel<<<1, 64, 0, st>>>(J);
         }

@@ -311,9 +311,28 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
     const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
     const Real dr = (Real)d;
     Real acc = 0;
-    for (int64_t q = b + lane; q < e; q += kWave) {
-        const Real t = dr * len[q];
-        acc = fma(t, (Real)2 * r[J.col[q]] + t, acc);
+    // U entries per lane in flight; each lane still adds its entries in
+    // ascending order, so the sum is the canonical one
+    constexpr int U = 8;
+    for (int64_t q0 = b + lane; q0 < e; q0 += (int64_t)kWave * U) {
+        int32_t cc[U];
+        Real ll[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int64_t q = q0 + (int64_t)c * kWave < e ? q0 + (int64_t)c * kWave : b;
+            cc[c] = J.col[q];
+            ll[c] = len[q];
+        }
+        Real rr[U];
+#pragma unroll
+        for (int c = 0; c < U; ++c) rr[c] = r[cc[c]];
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            if (q0 + (int64_t)c * kWave < e) {
+                const Real t = dr * ll[c];
+                acc = fma(t, (Real)2 * rr[c] + t, acc);
+            }
+        }
     }
     *p_out = p;
     *fn_out = fn;
@@ -322,38 +341,52 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
 }
 
 // One 64-ray tile of a from-scratch FP64 residual r = A f - Pm (Eq. 1,
-// Eq. 4): lane j sums ray t*64 + j over its entries in ascending pixel order
-// (fused multiply-add), loading 16 entries at a time so that every lane has
-// many loads in flight.  Writes r (chain precision), the tile's sum of
-// squares (butterfly over the 64 rays) and, if measure, its max |r_old - r64|.
-template <typename Real, int CH = 16>
+// Eq. 4), by one wavefront.  The four 16-lane quarters take the
+// tile's rays four at a time (quarter q the rays q*16 + i, i = 0..15); the
+// lanes of a quarter stride the ray's ray-major row by 16, so each load of
+// a quarter reads 16 consecutive entries, and each lane keeps one FP64
+// partial (its entries in ascending order, fused multiply-add).  An xor
+// butterfly over the quarter adds the 16 partials.  Lane j then holds ray
+// t*64 + j.  In-group and grid-wide rebuilds both run this function, so they
+// give the same bits.
+template <typename Real>
 __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int t, bool measure,
                              int lane)
 {
-    // CH entries of a ray are loaded at once; the sum runs over them in order,
-    // so CH changes the latency hiding, not the result
+    constexpr int U4 = 4;  // entries per lane in flight
     const Real* tl = (const Real*)J.t_len;
-    const int g = t * kWave + lane;
-    double acc = 0.0;
-    if (g < G) {
-        const int64_t b = J.t_row_ptr[g], e = J.t_row_ptr[g + 1];
-        for (int64_t q0 = b; q0 < e; q0 += CH) {
-            int32_t pc[CH];
-            Real lc[CH];
+    const int quarter = lane >> 4, ql = lane & 15;
+    double mine = 0.0;
+    for (int i = 0; i < 16; ++i) {
+        const int gi = t * kWave + quarter * 16 + i;
+        double acc = 0.0;
+        if (gi < G) {
+            const int64_t b = J.t_row_ptr[gi], e = J.t_row_ptr[gi + 1];
+            for (int64_t q0 = b + ql; q0 < e; q0 += 16 * U4) {
+                int32_t pc[U4];
+                Real lc[U4];
 #pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int64_t q = q0 + c < e ? q0 + c : b;
-                pc[c] = J.t_col[q];
-                lc[c] = tl[q];
+                for (int c = 0; c < U4; ++c) {
+                    const int64_t q = q0 + 16 * c < e ? q0 + 16 * c : b;
+                    pc[c] = J.t_col[q];
+                    lc[c] = tl[q];
+                }
+                double fv[U4];
+#pragma unroll
+                for (int c = 0; c < U4; ++c) fv[c] = J.f[pc[c]];
+#pragma unroll
+                for (int c = 0; c < U4; ++c)
+                    if (q0 + 16 * c < e) acc = fma((double)lc[c], fv[c], acc);
             }
-            double fv[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) fv[c] = J.f[pc[c]];
-#pragma unroll
-            for (int c = 0; c < CH; ++c)
-                if (q0 + c < e) acc = fma((double)lc[c], fv[c], acc);
         }
+        acc = acc + xor_partner<1>(acc);
+        acc = acc + xor_partner<2>(acc);
+        acc = acc + xor_partner<4>(acc);
+        acc = acc + xor_partner<8>(acc);
+        if (ql == i) mine = acc;
     }
+    const int g = t * kWave + lane;
+    const double acc = mine;
     double sq = 0.0, dr = 0.0;
     if (g < G) {
         const double r64 = acc - J.sino[g];
@@ -620,18 +653,20 @@ __device__ __forceinline__ void resync_in_group(const ChainJob& J, ChainState& c
 // any row length, any M
 // ---------------------------------------------------------------------------
 template <typename Real, bool LDS>
-__device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
+__device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, bool segmented = false)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
     const double KU = (double)J.K * (double)J.U;
     const int M = J.m_cand;
     Real* r = LDS ? (Real*)lds : (Real*)J.r;
-    ChainState cs = chain_setup<Real>(J, r, sh, lane, wave, NW);
+    // segmented (global residual only): the chain state comes from the carry
+    // and the chain returns when a resync is due, which then runs grid-wide
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
     Schedule sched;
-    sched.start(0, cs.n_steps, J.n_stages, cs.T0, cs.TN);
+    sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN);
     const bool f32 = sizeof(Real) == 4;
 
-    for (int64_t s = 0; s < cs.n_steps; ++s) {
+    for (int64_t s = cs.s_begin; s < cs.n_steps; ++s) {
         const double T = sched.at(s, cs.n_steps, J.n_stages);
         for (int m = wave; m < M; m += NW) {
             int32_t p;
@@ -663,14 +698,24 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh)
             if (lane == 0) J.f[p] = sh.fn[dn.ms];
         }
         count_decision(J, cs, dn, d_star, s);
-        if (f32 && J.resync_every > 0 && cs.since >= J.resync_every)
+        if (f32 && J.resync_every > 0 && cs.since >= J.resync_every) {
+            if (!LDS && segmented) {
+                __syncthreads();
+                save_carry(J, cs, s + 1, true);
+                return;
+            }
             resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+        }
         __syncthreads();
         if (cancel_seen(J, sh, s)) {
             cs.status = PILA_ECANCELED;
             cs.n_steps = s + 1;
             break;
         }
+    }
+    if (segmented) {
+        save_carry(J, cs, cs.n_steps, false);
+        return;
     }
     write_stats(J, cs);
 }

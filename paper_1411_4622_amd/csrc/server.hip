@@ -529,7 +529,8 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (!ring_shape(cfg.waves_per_chain)) return fail(PILA_EINVAL, "waves_per_chain must be 4 or 8");
     if (cfg.ring_size < 1 || (cfg.ring_size & (cfg.ring_size - 1)) || cfg.ring_size > (1 << 20))
         return fail(PILA_EINVAL, "ring_size must be a power of two up to 2^20");
-    if (cfg.max_slots < 0 || cfg.idle_us < 0) return fail(PILA_EINVAL, "negative max_slots or idle_us");
+    if (cfg.max_slots < 0 || cfg.idle_us < 0 || cfg.general_slots < 0)
+        return fail(PILA_EINVAL, "negative max_slots, idle_us or general_slots");
     if (cfg.mem_budget < ((size_t)1 << 20)) return fail(PILA_ENOMEM, "mem_budget below 1 MiB");
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
@@ -564,8 +565,9 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (s->scratch_blk.off == SIZE_MAX) return bail(fail(PILA_ENOMEM, "budget too small"));
     if (hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(PILA_EHIP, "cannot create the build stream"));
-    // the general body's queue takes an eighth of the slots, the pipelined one the rest
-    const int gen = std::max(1, cfg.max_slots / 8);
+    // the general body's queue takes general_slots (default an eighth), the pipelined one the rest
+    const int gen = cfg.general_slots > 0 ? cfg.general_slots : std::max(1, cfg.max_slots / 8);
+    if (gen >= cfg.max_slots) return bail(fail(PILA_EINVAL, "general_slots must be below max_slots"));
     int32_t rc = init_queue(s, s->q[0], ring_shape(cfg.waves_per_chain), cfg.max_slots - gen);
     if (rc == PILA_OK) rc = init_queue(s, s->q[1], general_shape(), gen);
     if (rc != PILA_OK) return bail(rc);

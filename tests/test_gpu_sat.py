@@ -201,3 +201,23 @@ def test_batch_matches_single_and_oracle(P):
         if prm.precision == "f64":
             o = _oracle_chain(sl, prm)
             assert np.max(np.abs(got - o[0])) <= 1e-9
+
+
+def test_segmented_general_body_matches_in_group(P):
+    """An FP32 chain the pipelined body cannot take (M = 40, 360 angles) with a
+    residual too large for LDS: sat_run runs it in segments with grid-wide
+    resyncs, the general batch kernel resyncs inside its workgroup; both must
+    give the same bits."""
+    sl = _slice(96, 360, 136, seed=61, masked=True, I0=1e4)
+    assert 360 * 136 * 4 > 160 * 1024
+    prm = P.SatParams(n_steps=3000, seed=17, m_cand=40, T0=None, q_auto=30, precision="f32",
+                      resync_every=200, n_stages=20)
+    f_seg, st_seg, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
+    assert st_seg["resyncs"] >= 2 and st_seg["chain_launches"] > 1
+    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    pl = P.pila_build(geom)
+    img = torch.from_numpy(sl.f0.copy()).cuda()
+    st = P.sat_run_batch([P.Job(pl, torch.from_numpy(sl.sino).cuda(), img, prm)],
+                         waves_per_chain=16, chains_per_cu=1)
+    assert np.array_equal(img.cpu().numpy(), f_seg)
+    assert st[0]["accepts"] == st_seg["accepts"] and st[0]["resyncs"] == st_seg["resyncs"]
