@@ -60,6 +60,21 @@ def _params(P, cfg, n_steps, seed, chain_id, precision="f32", nnz=0):
                        resync_every=resync_interval(cfg, nnz) if precision == "f32" else 0)
 
 
+def copy_probe(args, torch):
+    """Three device copies of a buffer of --copy-probe-mib MiB: the known-size
+    kernel that rocprofv3 --pmc runs scale FETCH_SIZE / WRITE_SIZE by."""
+    if not getattr(args, "copy_probe_mib", 0):
+        return
+    n = args.copy_probe_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d MiB read + %d MiB written per copy, 3 copies"
+        % (args.copy_probe_mib, args.copy_probe_mib))
+
+
 def _chain_bytes(n_steps, M, f_mean, accepts):
     # the single-chain kernel's per-estimate and per-accept bytes (FP32)
     return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
@@ -207,16 +222,19 @@ def run_c4(args, P, torch, datagen):
     sirt_bytes = n_it * (2 * 8.0 * pl.nnz + 8.0 * (G + NP) + 3 * 8.0 * NP + 2 * 8.0 * G)
     log("c4: SIRT %d iterations in %.3f s (%.1f GB/s algorithmic)"
         % (n_it, sirt_s, sirt_bytes / sirt_s / 1e9))
-    # SAT chain
-    steps = args.sat_steps or cfg["n_steps"]
-    prm = _params(P, cfg, steps, cfg["chain_seed"], 0)  # c4 keeps resync every 4096
-    img.copy_(f0)
-    e0.record()
-    st, _ = P.sat_run(pl, sino, prm, img)
-    e1.record()
-    e1.synchronize()
-    sat_s = e0.elapsed_time(e1) / 1e3
-    rm_sat = datagen.rmse(img.cpu().numpy(), sl.truth)
+    # SAT chain (--sat-steps 0 skips it)
+    steps = cfg["n_steps"] if args.sat_steps is None else args.sat_steps
+    sat_s, rm_sat = float("nan"), float("nan")
+    st = {"accepts": 0, "resyncs": 0, "max_drift_r": 0.0}
+    if steps > 0:
+        prm = _params(P, cfg, steps, cfg["chain_seed"], 0)  # c4 keeps resync every 4096
+        img.copy_(f0)
+        e0.record()
+        st, _ = P.sat_run(pl, sino, prm, img)
+        e1.record()
+        e1.synchronize()
+        sat_s = e0.elapsed_time(e1) / 1e3
+        rm_sat = datagen.rmse(img.cpu().numpy(), sl.truth)
     out = {
         "workload": "c4", "N": sl.N, "U": sl.U, "K": sl.K, "nnz": pl.nnz, "max_row": pl.max_row,
         "pila_build_s": build_s,
@@ -227,11 +245,13 @@ def run_c4(args, P, torch, datagen):
                               "unit": "GB/s", "frac": sirt_bytes / sirt_s / 1e9 / HBM_PEAK_GBS,
                               "algorithmic_bytes": sirt_bytes}},
         "sat": {"steps": steps, "M": cfg["M"], "seconds": sat_s,
-                "proposals_per_s": steps * cfg["M"] / sat_s, "us_per_step": 1e6 * sat_s / steps,
+                "proposals_per_s": steps * cfg["M"] / sat_s if steps else None,
+                "us_per_step": 1e6 * sat_s / steps if steps else None,
                 "accepts": st["accepts"], "resyncs": st["resyncs"], "max_drift_r": st["max_drift_r"],
                 "rmse": rm_sat},
         "data": "synthetic: seeded 30-ellipse phantom, analytic line integrals, Poisson noise I0=1e4",
     }
+    copy_probe(args, torch)
     print(json.dumps(out), flush=True)
     return 0
 
