@@ -256,10 +256,6 @@ int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const double* d_sin
                  double* h_cost, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Device information and errors                                             */
-/* ------------------------------------------------------------------------ */
-
-/* ------------------------------------------------------------------------ */
 /* Serving: many independent chains (one slice each, section II-A Steps 1-4  */
 /* per slice) admitted against a memory budget and run by resident          */
 /* workgroups that take new requests as earlier ones finish                  */
@@ -359,6 +355,10 @@ int32_t srv_get_status(srv_t* s, srv_status* st);
  * exit, and free everything.  NULL is accepted.
  */
 int32_t srv_destroy(srv_t* s);
+
+/* ------------------------------------------------------------------------ */
+/* Device information and errors                                             */
+/* ------------------------------------------------------------------------ */
 
 typedef struct pila_device_info {
     int32_t cu_count;
