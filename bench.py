@@ -122,8 +122,10 @@ def main() -> int:
     ap.add_argument("--sweeps", type=float, default=None, help="c3/c5: steps = sweeps x support")
     ap.add_argument("--sat-steps", type=int, default=None, help="c4: chain steps")
     ap.add_argument("--mem-budget-gb", type=float, default=96.0, help="c5: server memory budget")
-    ap.add_argument("--general-slots", type=int, default=96,
-                    help="c5: server slots for the general body (long rows)")
+    ap.add_argument("--general-slots", type=int, default=4,
+                    help="c5: server slots for the general body")
+    ap.add_argument("--long-slots", type=int, default=100,
+                    help="c5: server slots for the long-row body (720 angles)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

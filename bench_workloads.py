@@ -47,9 +47,10 @@ def _pool_map(fn, items, procs=16):
 def resync_interval(cfg, nnz):
     """Accepted nonzero changes between FP64 resyncs for the batch and serving
     workloads, which do not fix it: at least the configured 4096, and at
-    least nnz / 4096, so that the full-PILA rebuild (16 bytes per entry)
-    stays a small share of the chain's own traffic on large slices."""
-    return max(int(cfg["resync_every"]), int(nnz) // 4096)
+    least nnz / 1024.  Their resyncs run inside the chain's workgroup, where
+    a full-PILA rebuild reads about 17 GB/s (one CU, bound by its gathers);
+    nnz / 1024 keeps it near a tenth of the chain's time."""
+    return max(int(cfg["resync_every"]), int(nnz) // 1024)
 
 
 def _params(P, cfg, n_steps, seed, chain_id, precision="f32", nnz=0):
@@ -308,7 +309,8 @@ def run_c5(args, P, torch, datagen):
     log("c5: %d noisy sinograms on the device" % len(noisy))
 
     budget = int(args.mem_budget_gb * (1 << 30))
-    srv = P.Server(mem_budget=budget, idle_us=20000, general_slots=args.general_slots)
+    srv = P.Server(mem_budget=budget, idle_us=20000, general_slots=args.general_slots,
+                   long_slots=args.long_slots)
     t0 = time.perf_counter()
     for g in geoms.values():
         srv.prepare(g)

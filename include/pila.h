@@ -266,15 +266,19 @@ typedef struct srv_s srv_t; /* opaque server handle */
 typedef struct srv_config {
     size_t mem_budget;       /* device bytes the server allocates at creation and never
                                 exceeds: PILA cache, chain states, build scratch */
-    int32_t max_slots;       /* chains resident at once, one workgroup each;
+    int32_t max_slots;       /* chains resident at once, one workgroup each, >= 3;
                                 0 = compute units - 8 (the rest stay free for PILA builds) */
     int32_t waves_per_chain; /* 4 or 8 (0 = 8) */
     int32_t ring_size;       /* tickets submitted and not yet reaped; power of two, 0 = 1024 */
-    int32_t idle_us;         /* a workgroup that finds no work for this long exits; the
-                                server relaunches on the next submission (0 = 20000) */
-    int32_t general_slots;   /* of max_slots, those that run the general body (chains the
-                                pipelined body does not take: FP64, long rows, large M);
-                                0 = max_slots / 8 */
+    int32_t idle_us;         /* the resident workgroups exit when none of their chains runs
+                                and no request came for this long; the server relaunches
+                                them on the next submission (0 = 20000) */
+    int32_t general_slots;   /* of max_slots, those that run the general body (chains no
+                                other body takes: FP64, large M); 0 = max_slots / 16 */
+    int32_t long_slots;      /* of max_slots, those that run FP32 chains whose rows are too
+                                long for the pipelined body's registers (up to 1024
+                                entries); 0 = max_slots / 4.  The rest run the pipelined
+                                body */
 } srv_config;
 
 typedef struct srv_request {
@@ -342,7 +346,7 @@ int32_t srv_poll(srv_t* s, uint64_t ticket, int32_t* done, sat_stats* stats);
 
 /*
  * srv_cancel - ask the ticket's chain to stop: a waiting chain never starts,
- * a running one stops within 2048 steps.  Either way srv_poll then reports
+ * a running one stops within 1024 steps.  Either way srv_poll then reports
  * it done with stats.status = PILA_ECANCELED (the image holds the state
  * reached).  ENOTFOUND for unknown or reaped tickets.
  */

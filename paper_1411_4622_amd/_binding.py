@@ -81,7 +81,8 @@ class CSirtParams(C.Structure):
 
 class CSrvConfig(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_slots", C.c_int32), ("waves_per_chain", C.c_int32),
-                ("ring_size", C.c_int32), ("idle_us", C.c_int32), ("general_slots", C.c_int32)]
+                ("ring_size", C.c_int32), ("idle_us", C.c_int32), ("general_slots", C.c_int32),
+                ("long_slots", C.c_int32)]
 
 
 class CSrvRequest(C.Structure):
@@ -409,9 +410,10 @@ class Server:
     """
 
     def __init__(self, mem_budget: int, max_slots: int = 0, waves_per_chain: int = 0,
-                 ring_size: int = 0, idle_us: int = 0, general_slots: int = 0):
+                 ring_size: int = 0, idle_us: int = 0, general_slots: int = 0,
+                 long_slots: int = 0):
         cfg = CSrvConfig(int(mem_budget), int(max_slots), int(waves_per_chain), int(ring_size),
-                         int(idle_us), int(general_slots))
+                         int(idle_us), int(general_slots), int(long_slots))
         h = C.c_void_p()
         _check(load().srv_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -143,6 +143,19 @@ int64_t hybrid_lds(ChainJob* J, int64_t budget)
     return table + (int64_t)J->UL * J->Kc * rs;
 }
 
+bool long_allowed(const pila_geom* g, const pila_csr* c, const sat_params* p)
+{
+    return piped_allowed(g, c) && c->max_row <= kWave * kLongE && p->m_cand <= kPipedThreads / kWave;
+}
+
+int64_t long_lds(ChainJob* J, int64_t budget)
+{
+    const int64_t rs = J->precision == PILA_F32 ? 4 : 8;
+    J->UL = 0;
+    if (J->Kc > 0 && budget > 0) J->UL = (int32_t)std::min<int64_t>(budget / (J->Kc * rs), J->U);
+    return (int64_t)J->UL * J->Kc * rs;
+}
+
 int32_t set_lds(const void* k, int bytes)
 {
     PILA_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
@@ -168,6 +181,25 @@ __global__ __launch_bounds__(kPipedThreads) void sat_segment_kernel(ChainJob job
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
     run_chain_piped<float, false, CPW, E>(job, lds, sh, true);
+}
+
+// one chain, long-row body (rows of up to 64 E entries, one estimate per wavefront)
+template <typename Real, bool RLDS, int E>
+__global__ __launch_bounds__(kPipedThreads) void sat_long_kernel(ChainJob job)
+{
+    extern __shared__ __align__(16) char lds[];
+    __shared__ ChainShared sh;
+    run_chain_long<Real, RLDS, E>(job, lds, sh, false);
+}
+
+// one segment of a long-row chain whose FP64 resyncs run grid-wide between segments
+template <int E>
+__global__ __launch_bounds__(kPipedThreads) void sat_long_segment_kernel(ChainJob job)
+{
+    extern __shared__ __align__(16) char lds[];
+    __shared__ ChainShared sh;
+    if (job.carry->done || job.carry->status != PILA_OK) return;
+    run_chain_long<float, false, E>(job, lds, sh, true);
 }
 
 // one segment of a general-body chain (FP32, residual in global memory)
@@ -300,6 +332,26 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
     }
 }
 
+// Persistent batch of long-row FP32 chains (one estimate per wavefront)
+template <int E>
+__global__ __launch_bounds__(kPipedThreads) void sat_batch_long_kernel(
+    const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
+    int* __restrict__ ticket, int lds_bytes)
+{
+    extern __shared__ __align__(16) char lds[];
+    __shared__ ChainShared sh;
+    (void)lds_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) sh.ticket = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int j = sh.ticket;
+        __syncthreads();
+        if (j >= n_jobs) break;
+        const ChainJob J = jobs[order[j]];
+        run_chain_long<float, false, E>(J, lds, sh, false);
+    }
+}
+
 // Persistent batch for workgroups wider than the pipelined bodies allow:
 // every chain takes the general body.
 __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* __restrict__ jobs,
@@ -327,6 +379,7 @@ __global__ void zero_int_kernel(int* p)
 {
     p[0] = 0;
     p[1] = 0;
+    p[2] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -477,13 +530,17 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         piped_allowed(geom, csr) ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
                                  : nullptr;
     const bool resync = params->precision == PILA_F32 && params->resync_every > 0;
+    // rows too long for the pipelined body's registers: the long-row body
+    const bool lng = !ps && long_allowed(geom, csr, params);
     const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
-    const bool simple_seg = !ps && !r_in_lds && resync;
-    if (piped_seg || simple_seg) {
+    const bool long_seg = lng && !r_in_lds && resync;
+    const bool simple_seg = !ps && !lng && !r_in_lds && resync;
+    if (piped_seg || long_seg || simple_seg) {
         // FP32 residual in global memory: chain segments end at each resync,
         // which runs grid-wide; the host only enqueues, it never waits
         const int T = (int)((G + 63) / 64);
         const unsigned rb = (unsigned)std::min<int64_t>((T + 3) / 4, 4096);
+        const int long_bytes = long_seg ? (int)long_lds(&J, budget) : 0;
         sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 0);
         sat_setup_kernel<float><<<1, kPipedThreads, 0, st>>>(J);
         const int64_t n_seg = params->n_steps / params->resync_every + 1;
@@ -491,6 +548,9 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         for (int64_t k = 0; k < n_seg; ++k) {
             if (piped_seg) {
                 PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
+            } else if (long_seg) {
+                PILA_TRY(launch1(sat_long_segment_kernel<kLongE>, &J, params->m_cand * kWave, long_bytes,
+                                 st, &tm));
             } else {
                 PILA_TRY(tm.mark(st));
                 sat_simple_segment_kernel<<<1, sw * kWave, 0, st>>>(J);
@@ -503,6 +563,14 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     } else if (ps && (r_in_lds || table_lds <= budget)) {
         const int lds = r_in_lds ? (int)(G * rs) : table_lds;
         PILA_TRY(launch1(r_in_lds ? ps->k_lds : ps->k_glob, &J, waves * kWave, lds, st, &tm));
+    } else if (lng) {
+        const int lds = r_in_lds ? (int)(G * rs) : (int)long_lds(&J, budget);
+        ChainKernel k;
+        if (params->precision == PILA_F64)
+            k = r_in_lds ? sat_long_kernel<double, true, kLongE> : sat_long_kernel<double, false, kLongE>;
+        else
+            k = r_in_lds ? sat_long_kernel<float, true, kLongE> : sat_long_kernel<float, false, kLongE>;
+        PILA_TRY(launch1(k, &J, params->m_cand * kWave, lds, st, &tm));
     } else {
         waves = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         const int lds = r_in_lds ? (int)(G * rs) : 0;
@@ -532,7 +600,7 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
     clear_error();
     if (n_jobs < 0 || (n_jobs > 0 && !jobs) || !bytes) return fail(PILA_EINVAL, "bad batch arguments");
     size_t total = align256(sizeof(ChainJob) * (size_t)(n_jobs > 0 ? n_jobs : 1)) +
-                   align256(sizeof(int) * (2 + (size_t)(n_jobs > 0 ? n_jobs : 1)));
+                   align256(sizeof(int) * (3 + (size_t)(n_jobs > 0 ? n_jobs : 1)));
     for (int32_t j = 0; j < n_jobs; ++j) {
         PILA_TRY(check_geom(jobs[j].geom));
         total += chain_bytes(jobs[j].geom, &jobs[j].params);
@@ -554,7 +622,7 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     char* ws = (char*)d_ws;
     ChainJob* d_jobs = (ChainJob*)ws;
     int* d_ticket = (int*)(ws + align256(sizeof(ChainJob) * (size_t)n_jobs));
-    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (2 + (size_t)n_jobs));
+    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (3 + (size_t)n_jobs));
     std::vector<ChainJob> host((size_t)n_jobs);
     int max_m = 1, max_row = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
@@ -598,18 +666,32 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         const int per_wg = (int)(prop.sharedMemPerBlock / (size_t)per_cu) - (int)sizeof(ChainShared) - 512;
         lds = per_wg > 0 ? (per_wg & ~255) : 0;
     }
-    // split the chains: pipelined (FP32, fits the shape and the LDS table) and general
-    std::vector<int> piped_ids, simple_ids;
+    // split the chains: pipelined (FP32, fits the shape and the LDS table),
+    // long rows (FP32, one estimate per wavefront) and general
+    std::vector<int> piped_ids, long_ids, simple_ids;
     for (int32_t j = 0; j < n_jobs; ++j) {
         ChainJob& J = host[j];
         bool ok = bs && J.precision == PILA_F32 && piped_allowed(jobs[j].geom, jobs[j].csr) &&
                   J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw;
         if (ok) ok = hybrid_lds(&J, lds) <= lds;  // LDS part of the residual
-        (ok ? piped_ids : simple_ids).push_back(j);
+        if (ok) {
+            piped_ids.push_back(j);
+            continue;
+        }
+        if (J.precision == PILA_F32 && waves * kWave <= kPipedThreads && J.m_cand <= waves &&
+            long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
+            long_lds(&J, lds);
+            long_ids.push_back(j);
+            continue;
+        }
+        J.UL = 0;
+        simple_ids.push_back(j);
     }
     std::vector<int> order(piped_ids);
+    order.insert(order.end(), long_ids.begin(), long_ids.end());
     order.insert(order.end(), simple_ids.begin(), simple_ids.end());
-    int* d_order = d_ticket + 2;  // [0]: pipelined ticket, [1]: general ticket, then the order
+    // [0]: pipelined ticket, [1]: general ticket, [2]: long-row ticket, then the order
+    int* d_order = d_ticket + 3;
     PILA_HIP(hipMemcpyAsync(d_jobs, host.data(), sizeof(ChainJob) * host.size(), hipMemcpyHostToDevice, st));
     PILA_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
     zero_int_kernel<<<1, 1, 0, st>>>(d_ticket);
@@ -624,9 +706,19 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         PILA_TRY(set_lds((const void*)bs->k, lds));
         PILA_HIP(hipLaunchKernel((const void*)bs->k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
     }
+    if (!long_ids.empty()) {
+        int n_arg = (int)long_ids.size();
+        const int* order_arg = d_order + piped_ids.size();
+        int* ticket_arg = d_ticket + 2;
+        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
+        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
+        const void* k = (const void*)sat_batch_long_kernel<kLongE>;
+        PILA_TRY(set_lds(k, lds));
+        PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
+    }
     if (!simple_ids.empty()) {
         int n_arg = (int)simple_ids.size();
-        const int* order_arg = d_order + piped_ids.size();
+        const int* order_arg = d_order + piped_ids.size() + long_ids.size();
         int* ticket_arg = d_ticket + 1;
         void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
         const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);

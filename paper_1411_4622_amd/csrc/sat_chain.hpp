@@ -137,15 +137,14 @@ __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
 // Cancellation of a served chain: thread 0 reads the host word every
 // kCancelEvery steps before a barrier, every thread reads its copy after a
 // later barrier of the same step, so the whole workgroup leaves together.
-// The read is an acquire at system scope: its cache invalidation makes the
-// next read fetch the word from host memory again, so a cancellation is seen
-// within two checks.
+// The read is a system-scope load of coherent host memory (it reaches host
+// memory each time); it carries no ordering, so it invalidates no cache.
 constexpr int64_t kCancelEvery = 1024;
 
 __device__ __forceinline__ void cancel_probe(const ChainJob& J, ChainShared& sh, int64_t s)
 {
     if (J.cancel && (s & (kCancelEvery - 1)) == 0 && threadIdx.x == 0)
-        sh.stop = __hip_atomic_load(J.cancel, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) == J.cancel_tag;
+        sh.stop = __hip_atomic_load(J.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == J.cancel_tag;
 }
 __device__ __forceinline__ bool cancel_seen(const ChainJob& J, const ChainShared& sh, int64_t s)
 {
@@ -1058,6 +1057,214 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         }
         if (++s >= n_steps) break;
         if (step(C, A, B, s)) {
+            if (SERVED && cancelled) break;
+            return;
+        }
+        ++s;
+    }
+    if (!RLDS) {
+        __syncthreads();
+        lds_residual_store<Real>(J, r, rl);
+    }
+    if (segmented) {
+        save_carry(J, cs, n_steps, false);
+        return;
+    }
+    write_stats(J, cs);
+}
+
+// ---------------------------------------------------------------------------
+// long rows: one estimate per wavefront, rows of up to 64 E entries in
+// registers one step ahead; residual values are read at the start of each
+// step (after the previous step's scatter), so no patch table is needed.
+// The residual lives in LDS for angles u < UL (over bins k_lo .. k_lo+Kc-1,
+// at the start of the dynamic LDS) and in global memory otherwise, or wholly
+// in LDS (RLDS).  Same canonical sums and decision as the other bodies.
+// ---------------------------------------------------------------------------
+template <typename Real, int E>
+struct LongRow {
+    int32_t col[E];
+    Real len[E];
+    int32_t p, n;
+    double delta, N1, lnN1;
+};
+
+template <typename Real, bool RLDS, int E, bool SERVED = false>
+__device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
+{
+    constexpr int BL = kWave;  // steps per block of draws: lane j <-> step base + j
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+    const double KU = (double)J.K * (double)J.U;
+    const int M = J.m_cand;
+    const bool active = wave < M;
+    Real* r = RLDS ? (Real*)lds : (Real*)J.r;
+    Real* rl = (Real*)lds;
+    const Real* lenp = (const Real*)J.len;
+
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
+    const int64_t n_steps = cs.n_steps;
+    const int64_t s_begin = cs.s_begin;
+    if (!RLDS) lds_residual_load<Real>(J, r, rl);
+    Schedule sched;
+    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN);
+
+    Draws cur, nxt;
+    auto fill = [&](Draws& D, int64_t base) {
+        D.base = base;
+        const int64_t s = base + lane;
+        D.p = 0;
+        D.n = 0;
+        D.b = 0;
+        D.delta = 0.0;
+        D.N1 = 0.0;
+        D.lnN1 = 0.0;
+        uint64_t k0 = lane0(J.seed), k1 = lane0(J.chain_id);
+        asm volatile("" : "+s"(k0), "+s"(k1));
+        if (s < n_steps) {
+            if (active) {
+                const Words4 w = philox4x64(k0, k1, (uint64_t)s, (uint64_t)wave, 0, 0);
+                D.p = J.support[__umul64hi(w.w0, (uint64_t)J.P)];
+                D.delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+                const int64_t b0 = J.row_ptr[D.p];
+                D.b = (uint32_t)b0;
+                D.n = (int32_t)(J.row_ptr[D.p + 1] - b0);
+            }
+            D.N1 = unit53(philox4x64(k0, k1, (uint64_t)s, 0, 1, 0).w0);
+            D.lnN1 = log(D.N1);
+        }
+    };
+    cur.base = nxt.base = -1;
+    auto prefetch = [&](LongRow<Real, E>& S, int64_t t) {
+        if (t >= n_steps) {
+            S.p = 0;
+            S.n = 0;
+            S.delta = S.N1 = S.lnN1 = 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                S.col[e] = 0;
+                S.len[e] = (Real)0;
+            }
+            return;
+        }
+        const int64_t base = t - t % BL;
+        if (cur.base != base) {
+            if (nxt.base == base)
+                cur = nxt;
+            else
+                fill(cur, base);
+        }
+        const int j = (int)(t - base);
+        if (j == BL / 2 && base + BL < n_steps) fill(nxt, base + BL);
+        S.p = __shfl(cur.p, j, kWave);
+        S.n = __shfl(cur.n, j, kWave);
+        const uint32_t b = (uint32_t)__shfl((int)cur.b, j, kWave);
+        S.delta = __shfl(cur.delta, j, kWave);
+        S.N1 = __shfl(cur.N1, j, kWave);
+        S.lnN1 = __shfl(cur.lnN1, j, kWave);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int q = lane + e * kWave;
+            const uint32_t at = q < S.n ? b + (uint32_t)q : 0u;
+            S.col[e] = ld32(J.col, at);
+            S.len[e] = ld32(lenp, at);
+        }
+    };
+    // residual value of ray g: LDS part (angles u < UL) or global memory
+    auto rget = [&](int32_t g, int* lidx) -> Real {
+        if (RLDS) {
+            *lidx = g;
+            return r[g];
+        }
+        const int u = (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s);
+        if (u < J.UL) {
+            *lidx = u * J.Kc + (g - u * J.K - J.k_lo);
+            return rl[*lidx];
+        }
+        *lidx = -1;
+        return ld32((const Real*)r, (uint32_t)g);
+    };
+
+    LongRow<Real, E> A, B;
+    prefetch(A, s_begin);
+    __syncthreads();  // setup (residual, LDS part, temperatures) complete
+    bool cancelled = false;
+    // returns true when the chain stops here (segment end or cancellation)
+    auto step = [&](LongRow<Real, E>& X, LongRow<Real, E>& Y, int64_t s)
+                    __attribute__((always_inline)) -> bool {
+        const double T = sched.at(s, n_steps, J.n_stages);
+        const double invT = 1.0 / T;
+        prefetch(Y, s + 1);
+        Real rv[E];
+        int li[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) rv[e] = rget(X.col[e], &li[e]);
+        const double fo = J.f[X.p];
+        double fn = fo + X.delta;
+        if (fn < J.f_min) fn = J.f_min;
+        if (fn > J.f_max) fn = J.f_max;
+        const double d = fn - fo;
+        const Real dr = (Real)d;
+        Real part[1] = {(Real)0};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const Real t = (lane + e * kWave < X.n) ? dr * X.len[e] : (Real)0;
+            part[0] = fma(t, (Real)2 * rv[e] + t, part[0]);
+        }
+        const Real S = canon_sum<kWave>(part);
+        if (active && lane == 0) {
+            sh.S[wave] = (double)S;
+            sh.d[wave] = d;
+        }
+        const double co = sqrt(cs.sse / KU);
+        if (SERVED) cancel_probe(J, sh, s);
+        __syncthreads();
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, X.N1, X.lnN1);
+        const double d_star = uniform_f64(sh.d[dn.ms]);
+        const bool changed = dn.accept && d_star != 0.0;
+        if (changed && dn.ms == wave) {  // the owner of the winner applies Eq. 6
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (lane + e * kWave < X.n) {
+                    const Real rn = rv[e] + dr * X.len[e];
+                    if (RLDS)
+                        r[X.col[e]] = rn;
+                    else if (li[e] >= 0)
+                        rl[li[e]] = rn;
+                    else
+                        st32(r, (uint32_t)X.col[e], rn);
+                }
+            }
+            if (lane == 0) J.f[X.p] = fn;
+        }
+        count_decision(J, cs, dn, d_star, s);
+        if (sizeof(Real) == 4 && J.resync_every > 0 && cs.since >= J.resync_every) {
+            if (!RLDS) {
+                __syncthreads();
+                lds_residual_store<Real>(J, r, rl);
+            }
+            if (segmented) {
+                save_carry(J, cs, s + 1, true);
+                return true;
+            }
+            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            if (!RLDS) lds_residual_load<Real>(J, r, rl);
+        }
+        __syncthreads();
+        if (SERVED && cancel_seen(J, sh, s)) {
+            cs.status = PILA_ECANCELED;
+            cs.n_steps = s + 1;
+            cancelled = true;
+            return true;
+        }
+        return false;
+    };
+    for (int64_t s = s_begin; s < n_steps;) {
+        if (step(A, B, s)) {
+            if (SERVED && cancelled) break;
+            return;
+        }
+        if (++s >= n_steps) break;
+        if (step(B, A, s)) {
             if (SERVED && cancelled) break;
             return;
         }

@@ -21,6 +21,12 @@ int device_props(hipDeviceProp_t* prop);
 bool piped_allowed(const pila_geom* g, const pila_csr* c);
 // LDS bytes of a pipelined chain with the residual partly in LDS; sets J->UL
 int64_t hybrid_lds(ChainJob* J, int64_t budget);
+// rows per lane in registers of the long-row body (rows up to 64 kLongE entries)
+constexpr int kLongE = 16;
+// whether the long-row body takes this chain (one estimate per wavefront)
+bool long_allowed(const pila_geom* g, const pila_csr* c, const sat_params* p);
+// LDS bytes of a long-row chain with the residual partly in LDS; sets J->UL
+int64_t long_lds(ChainJob* J, int64_t budget);
 int32_t set_lds(const void* k, int bytes);
 
 // pila_build with a caller-supplied device scratch of pila_build_scratch(geom) bytes

@@ -16,8 +16,10 @@
 //    start in order and each exactly once; it records claimed, runs the
 //    chain, writes the stats and then done = ticket + 1 with a system-scope
 //    release (which also makes the chain's image writes visible);
-//  * a workgroup that finds no work for idle_us exits; the host relaunches
-//    the kernel on a later call when tickets wait and it has exited.
+//  * a workgroup that finds no work for idle_us while no chain of its queue
+//    runs (a second device counter counts finished chains) exits; the host
+//    relaunches the kernel on a later call when tickets wait and it has
+//    exited.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -53,9 +55,12 @@ constexpr int kJobWords = (int)(sizeof(ChainJob) / 4);
 static_assert(sizeof(ChainJob) % 4 == 0, "descriptor is copied in 32-bit words");
 static_assert(sizeof(sat_stats) % 8 == 0, "stats are copied in 64-bit words");
 
-// GENERAL = false: pipelined body of shape (CPW, E), FP32 chains only;
-// GENERAL = true: the general body (any row length, M, precision).
-template <bool GENERAL, int CPW, int E>
+// BODY kPiped: pipelined body of shape (CPW, E), FP32 chains only; kLong:
+// the long-row body (FP32, one estimate per wavefront); kGeneral: the
+// general body (any row length, M, precision).
+enum { kPiped = 0, kGeneral = 1, kLong = 2 };
+
+template <int BODY, int CPW, int E>
 __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, RingSlot* slots,
                                                                  uint32_t mask,
                                                                  unsigned long long* head,
@@ -72,20 +77,29 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
             int64_t idle = 0;
             for (;;) {
                 if (__hip_atomic_load(&ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) break;
-                // acquire: the slot written before this tail, and any data the
-                // request names, are seen by this workgroup's later loads
+                // polled without ordering: an acquire invalidates this XCD's
+                // caches, which the chains running beside this workgroup use
                 const unsigned long long t =
-                    __hip_atomic_load(&ctl->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                    __hip_atomic_load(&ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 const unsigned long long h =
                     __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (h < t) {
                     if (atomicCAS(head, h, h + 1) == h) {
+                        // acquire once per claim: the slot written before the
+                        // tail, and the data the request names, are seen by
+                        // this workgroup's later loads
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
                         got = (long long)h;
                         break;
                     }
                     continue;
                 }
-                if (++idle > idle_polls) break;
+                // exit only when idle and no chain of this queue runs: a new
+                // request may follow any running one, and an exited
+                // workgroup does not come back until the kernel ends
+                if (++idle > idle_polls &&
+                    __hip_atomic_load(head + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == h)
+                    break;
                 __builtin_amdgcn_s_sleep(127);
             }
             got_s = got;
@@ -107,8 +121,10 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
         const ChainJob J = uniform_job(*(const ChainJob*)desc);
         const bool cancelled = __builtin_amdgcn_readfirstlane(flags_s[0]) != 0;
         if (!cancelled) {
-            if constexpr (!GENERAL)
+            if constexpr (BODY == kPiped)
                 run_chain_piped<float, false, CPW, E, true>(J, lds, sh, false);
+            else if constexpr (BODY == kLong)
+                run_chain_long<float, false, E, true>(J, lds, sh, false);
             else if (J.precision == PILA_F32)
                 run_chain_simple_dispatch<float>(J, lds, lds_bytes, sh);
             else
@@ -129,6 +145,7 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
                 __hip_atomic_store(d64 + i, s64[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             // release: stats and every image write of the chain before done
             __hip_atomic_store(&sl->done, (uint64_t)got + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            atomicAdd(head + 1, 1ull);  // chains finished by this queue
         }
         __syncthreads();
     }
@@ -144,8 +161,8 @@ struct RingShape {
 // the pipelined shape of each workgroup width: M <= waves * cpw, rows <= 64 / cpw * e
 const RingShape* ring_shape(int waves)
 {
-    static const RingShape shapes[] = {{8, 1, 8, srv_ring_kernel<false, 1, 8>},
-                                       {4, 2, 8, srv_ring_kernel<false, 2, 8>}};
+    static const RingShape shapes[] = {{8, 1, 8, srv_ring_kernel<kPiped, 1, 8>},
+                                       {4, 2, 8, srv_ring_kernel<kPiped, 2, 8>}};
     for (const RingShape& s : shapes)
         if (s.waves == waves) return &s;
     return nullptr;
@@ -154,7 +171,14 @@ const RingShape* ring_shape(int waves)
 // the general body's queue: workgroups of 8 wavefronts
 const RingShape* general_shape()
 {
-    static const RingShape g = {8, 1, 0, srv_ring_kernel<true, 1, 1>};
+    static const RingShape g = {8, 1, 0, srv_ring_kernel<kGeneral, 1, 1>};
+    return &g;
+}
+
+// the long-row body's queue: 8 wavefronts, one estimate each, rows of up to 64 kLongE entries
+const RingShape* long_shape()
+{
+    static const RingShape g = {8, 1, kLongE, srv_ring_kernel<kLong, 1, kLongE>};
     return &g;
 }
 
@@ -295,7 +319,7 @@ struct srv_s {
     int64_t idle_polls = 0;
     int64_t reaped = 0;
     uint64_t use_clock = 0;
-    Queue q[2];  // 0: pipelined body, 1: general body; ticket = local << 1 | queue
+    Queue q[3];  // kPiped, kGeneral, kLong bodies; ticket = local << 2 | queue
     std::list<std::unique_ptr<PilaEntry>> cache;
 };
 
@@ -446,8 +470,8 @@ int32_t progress_queue(srv_t* s, Queue& q)
 
 int32_t progress(srv_t* s)
 {
-    PILA_TRY(progress_queue(s, s->q[0]));
-    return progress_queue(s, s->q[1]);
+    for (Queue& q : s->q) PILA_TRY(progress_queue(s, q));
+    return PILA_OK;
 }
 
 void release_request(srv_t* s, Request& rq)
@@ -462,8 +486,9 @@ void release_request(srv_t* s, Request& rq)
 // queue and slot of a live ticket
 int32_t find_ticket(srv_t* s, uint64_t t, Queue** q, uint64_t* local)
 {
-    Queue& qq = s->q[t & 1];
-    const uint64_t l = t >> 1;
+    if ((t & 3) > 2) return fail(PILA_ENOTFOUND, "ticket %llu is unknown", (unsigned long long)t);
+    Queue& qq = s->q[t & 3];
+    const uint64_t l = t >> 2;
     if (l >= qq.next || qq.next - l > (uint64_t)s->cfg.ring_size || !qq.reqs[l & s->mask].live)
         return fail(PILA_ENOTFOUND, "ticket %llu is unknown or already reaped", (unsigned long long)t);
     *q = &qq;
@@ -529,16 +554,16 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (!ring_shape(cfg.waves_per_chain)) return fail(PILA_EINVAL, "waves_per_chain must be 4 or 8");
     if (cfg.ring_size < 1 || (cfg.ring_size & (cfg.ring_size - 1)) || cfg.ring_size > (1 << 20))
         return fail(PILA_EINVAL, "ring_size must be a power of two up to 2^20");
-    if (cfg.max_slots < 0 || cfg.idle_us < 0 || cfg.general_slots < 0)
-        return fail(PILA_EINVAL, "negative max_slots, idle_us or general_slots");
+    if (cfg.max_slots < 0 || cfg.idle_us < 0 || cfg.general_slots < 0 || cfg.long_slots < 0)
+        return fail(PILA_EINVAL, "negative max_slots, idle_us, general_slots or long_slots");
     if (cfg.mem_budget < ((size_t)1 << 20)) return fail(PILA_ENOMEM, "mem_budget below 1 MiB");
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
-    if (cfg.max_slots == 0) cfg.max_slots = std::max(2, prop.multiProcessorCount - 8);
-    if (cfg.max_slots < 2) return fail(PILA_EINVAL, "max_slots must be at least 2");
+    if (cfg.max_slots == 0) cfg.max_slots = std::max(3, prop.multiProcessorCount - 8);
+    if (cfg.max_slots < 3) return fail(PILA_EINVAL, "max_slots must be at least 3");
     // one resident workgroup per compute unit: all LDS but the static part
     size_t stat = 0;
-    for (const RingShape* sh : {ring_shape(cfg.waves_per_chain), general_shape()}) {
+    for (const RingShape* sh : {ring_shape(cfg.waves_per_chain), general_shape(), long_shape()}) {
         hipFuncAttributes fa;
         PILA_HIP(hipFuncGetAttributes(&fa, (const void*)sh->k));
         stat = std::max(stat, fa.sharedSizeBytes);
@@ -565,11 +590,15 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (s->scratch_blk.off == SIZE_MAX) return bail(fail(PILA_ENOMEM, "budget too small"));
     if (hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(PILA_EHIP, "cannot create the build stream"));
-    // the general body's queue takes general_slots (default an eighth), the pipelined one the rest
-    const int gen = cfg.general_slots > 0 ? cfg.general_slots : std::max(1, cfg.max_slots / 8);
-    if (gen >= cfg.max_slots) return bail(fail(PILA_EINVAL, "general_slots must be below max_slots"));
-    int32_t rc = init_queue(s, s->q[0], ring_shape(cfg.waves_per_chain), cfg.max_slots - gen);
-    if (rc == PILA_OK) rc = init_queue(s, s->q[1], general_shape(), gen);
+    // general_slots (default a sixteenth) and long_slots (default a quarter)
+    // for those bodies, the pipelined body the rest
+    const int gen = cfg.general_slots > 0 ? cfg.general_slots : std::max(1, cfg.max_slots / 16);
+    const int lng = cfg.long_slots > 0 ? cfg.long_slots : std::max(1, cfg.max_slots / 4);
+    if (gen + lng >= cfg.max_slots)
+        return bail(fail(PILA_EINVAL, "general_slots + long_slots must be below max_slots"));
+    int32_t rc = init_queue(s, s->q[kPiped], ring_shape(cfg.waves_per_chain), cfg.max_slots - gen - lng);
+    if (rc == PILA_OK) rc = init_queue(s, s->q[kGeneral], general_shape(), gen);
+    if (rc == PILA_OK) rc = init_queue(s, s->q[kLong], long_shape(), lng);
     if (rc != PILA_OK) return bail(rc);
     if (hipStreamSynchronize(s->build_stream) != hipSuccess)
         return bail(fail(PILA_EHIP, "cannot clear the claim counters"));
@@ -599,14 +628,19 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     PilaEntry* e = nullptr;
     PILA_TRY(cache_get(s, req->geom, &e));
     PILA_TRY(check_params(&e->geom, &e->csr, &req->params));
-    // queue: the pipelined body when the chain fits its shape and LDS
-    const RingShape* ps = s->q[0].shape;
+    // queue: the pipelined body when the chain fits its shape and LDS, the
+    // long-row body for longer rows, else the general body
+    const RingShape* ps = s->q[kPiped].shape;
     ChainJob probe = make_job(&e->geom, &e->csr, req->d_sino, &req->params, req->d_image, nullptr);
-    bool piped = req->params.precision == PILA_F32 && piped_allowed(&e->geom, &e->csr) &&
-                 req->params.m_cand <= ps->waves * ps->cpw &&
-                 e->csr.max_row <= (kWave / ps->cpw) * ps->e &&
-                 hybrid_lds(&probe, s->lds_bytes) <= s->lds_bytes;
-    Queue& q = s->q[piped ? 0 : 1];
+    const bool f32 = req->params.precision == PILA_F32;
+    int qi = kGeneral;
+    if (f32 && piped_allowed(&e->geom, &e->csr) && req->params.m_cand <= ps->waves * ps->cpw &&
+        e->csr.max_row <= (kWave / ps->cpw) * ps->e && hybrid_lds(&probe, s->lds_bytes) <= s->lds_bytes)
+        qi = kPiped;
+    else if (f32 && long_allowed(&e->geom, &e->csr, &req->params) &&
+             req->params.m_cand <= long_shape()->waves)
+        qi = kLong;
+    Queue& q = s->q[qi];
     const uint64_t l = q.next;
     Request& rq = q.reqs[l & s->mask];
     if (rq.live) return fail(PILA_EBUSY, "all %d slots of the ring hold unreaped tickets", s->cfg.ring_size);
@@ -618,7 +652,8 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     Block ws;
     if (!alloc_evicting(s, cb, e, &ws)) return fail(PILA_EBUSY, "no room for the chain state now");
     ChainJob J = make_job(&e->geom, &e->csr, req->d_sino, &req->params, req->d_image, s->arena.at(ws.off));
-    if (piped) hybrid_lds(&J, s->lds_bytes);
+    if (qi == kPiped) hybrid_lds(&J, s->lds_bytes);
+    if (qi == kLong) long_lds(&J, s->lds_bytes);
     RingSlot& sl = q.slots[l & s->mask];
     J.cancel = &q.d_slots[l & s->mask].cancel;
     J.cancel_tag = l + 1;
@@ -634,7 +669,7 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     rq.live = true;
     q.next = l + 1;
     __atomic_store_n(&q.ctl->tail, l + 1, __ATOMIC_RELEASE);
-    *ticket = (l << 1) | (piped ? 0u : 1u);
+    *ticket = (l << 2) | (uint64_t)qi;
     return progress(s);
 }
 
@@ -675,14 +710,14 @@ extern "C" int32_t srv_get_status(srv_t* s, srv_status* st)
     if (!s || !st) return fail(PILA_EINVAL, "server or status is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     PILA_TRY(progress(s));
-    st->submitted = (int64_t)(s->q[0].next + s->q[1].next);
+    st->submitted = (int64_t)(s->q[0].next + s->q[1].next + s->q[2].next);
     st->reaped = s->reaped;
     st->in_flight = st->submitted - s->reaped;
-    st->launches = s->q[0].launches + s->q[1].launches;
+    st->launches = s->q[0].launches + s->q[1].launches + s->q[2].launches;
     st->bytes_used = s->arena.used();
     st->bytes_budget = s->arena.size();
     st->pila_cached = (int32_t)s->cache.size();
-    st->kernel_running = (queue_running(s->q[0]) || queue_running(s->q[1])) ? 1 : 0;
+    st->kernel_running = (queue_running(s->q[0]) || queue_running(s->q[1]) || queue_running(s->q[2])) ? 1 : 0;
     return PILA_OK;
 }
 

@@ -131,11 +131,11 @@ def test_server_argument_errors(P):
     h = C.c_void_p()
     E = P._binding.PILA_EINVAL
     assert lib.srv_create(None, C.byref(h)) == E
-    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 5, 0, 0, 0)), C.byref(h)) == E
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 5, 0, 0, 0, 0)), C.byref(h)) == E
     assert "waves_per_chain" in P.last_error()
-    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 8, 3, 0, 0)), C.byref(h)) == E
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 30, 0, 8, 3, 0, 0, 0)), C.byref(h)) == E
     assert "power of two" in P.last_error()
-    assert lib.srv_create(C.byref(CSrvConfig(1 << 10, 0, 8, 0, 0, 0)), C.byref(h)) == P._binding.PILA_ENOMEM
+    assert lib.srv_create(C.byref(CSrvConfig(1 << 10, 0, 8, 0, 0, 0, 0)), C.byref(h)) == P._binding.PILA_ENOMEM
     done = C.c_int32(0)
     assert lib.srv_poll(None, 0, C.byref(done), None) == E
     assert lib.srv_cancel(None, 0) == E

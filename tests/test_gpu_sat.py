@@ -221,3 +221,42 @@ def test_segmented_general_body_matches_in_group(P):
                          waves_per_chain=16, chains_per_cu=1)
     assert np.array_equal(img.cpu().numpy(), f_seg)
     assert st[0]["accepts"] == st_seg["accepts"] and st[0]["resyncs"] == st_seg["resyncs"]
+
+
+def test_long_rows_fp64_match_oracle(P):
+    """420 angles: rows of more than 512 entries, which the long-row body
+    (one estimate per wavefront, rows in registers) takes."""
+    sl = _slice(16, 420, 23, seed=71, masked=True, I0=1e4)
+    prm = P.SatParams(n_steps=4000, seed=19, chain_id=3, m_cand=6, T0=None, q_auto=30,
+                      n_stages=40, delta_max=0.05)
+    g = _gpu_chain(P, sl, "f64", prm)
+    assert g[1]["chain_launches"] == 1
+    _compare_fp64(g, _oracle_chain(sl, prm))
+
+
+def test_long_rows_fp32_alone_batched_served_agree(P):
+    """FP32 long rows with the residual partly in LDS: alone (segments with
+    grid-wide resyncs), in a batch and served (in-workgroup resyncs) give the
+    same bits."""
+    sl = _slice(80, 420, 114, seed=73, masked=True, I0=1e4)
+    assert 420 * 114 * 4 > 160 * 1024
+    prm = P.SatParams(n_steps=6000, seed=23, chain_id=1, m_cand=8, T0=None, q_auto=30,
+                      precision="f32", resync_every=300, n_stages=30)
+    f_alone, st_alone, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
+    assert st_alone["resyncs"] >= 2 and st_alone["chain_launches"] > 1
+    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    pl = P.pila_build(geom)
+    assert pl.max_row > 512
+    sino = torch.from_numpy(sl.sino).cuda()
+    img = torch.from_numpy(sl.f0.copy()).cuda()
+    st = P.sat_run_batch([P.Job(pl, sino, img, prm)], waves_per_chain=8, chains_per_cu=1)
+    assert np.array_equal(img.cpu().numpy(), f_alone)
+    assert st[0]["accepts"] == st_alone["accepts"]
+    img2 = torch.from_numpy(sl.f0.copy()).cuda()
+    torch.cuda.current_stream().synchronize()
+    with P.Server(mem_budget=1 << 30, max_slots=6, idle_us=5000) as srv:
+        t = srv.submit(geom, sino, img2, prm)
+        assert t is not None and t & 3 == 2, "long-row queue"
+        while srv.poll(t) is None:
+            pass
+    assert np.array_equal(img2.cpu().numpy(), f_alone)

@@ -59,9 +59,11 @@ def _wait(srv, ticket, timeout=120.0):
 
 
 # (N, U, K, precision, M): FP32 M <= 8 with short rows take the pipelined
-# queue; M = 16 and FP64 take the general queue
+# queue; M = 16 and FP64 take the general queue; 420 angles (rows of more
+# than 512 entries) take the long-row queue
 SPECS = [(24, 30, 35, "f32", 4), (32, 45, 47, "f32", 8), (20, 18, 29, "f64", 3),
-         (28, 36, 40, "f32", 16), (40, 60, 57, "f32", 8), (16, 12, 23, "f64", 8)]
+         (28, 36, 40, "f32", 16), (40, 60, 57, "f32", 8), (16, 12, 23, "f64", 8),
+         (24, 420, 35, "f32", 6)]
 
 
 def _requests(P, specs, steps0=2000):
@@ -89,8 +91,8 @@ def test_served_chains_match_lone_chains(P):
     reqs = _requests(P, SPECS)
     with P.Server(mem_budget=GiB, max_slots=16, idle_us=5000) as srv:
         tickets = [_submit(P, srv, *r) for r in reqs]
-        queues = {t & 1 for t, _ in tickets}
-        assert queues == {0, 1}, "both queues are exercised"
+        queues = {t & 3 for t, _ in tickets}
+        assert queues == {0, 1, 2}, "all three queues are exercised"
         stats = [_wait(srv, t) for t, _ in tickets]
         for (sl, dt, prm), (t, img), st in zip(reqs, tickets, stats):
             print("ticket %d N=%d M=%d %s" % (t, sl.N, prm.m_cand, dt), flush=True)
@@ -155,8 +157,9 @@ def test_ring_slots_are_reused(P):
 def test_cancel_waiting_and_running(P):
     sl = _slice(48, 60, 68, seed=77)
     long_prm = _params(P, 1, 8, "f32", 5_000_000)
-    # two slots: one pipelined workgroup, one general; the second long chain waits
-    with P.Server(mem_budget=GiB, max_slots=2, idle_us=5000) as srv:
+    # three slots: one pipelined workgroup, one general, one long-row; the
+    # second pipelined chain waits
+    with P.Server(mem_budget=GiB, max_slots=3, idle_us=5000) as srv:
         t1, img1 = _submit(P, srv, sl, "f32", long_prm)
         t2, img2 = _submit(P, srv, sl, "f32", _params(P, 2, 8, "f32", 5_000_000))
         time.sleep(0.5)
