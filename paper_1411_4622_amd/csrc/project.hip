@@ -319,6 +319,155 @@ __global__ __launch_bounds__(256) void tile_back_kernel(int N, int U, int K, int
     if (p >= 0 && rp[p + 1] > rp[p]) f[p] = f[p] + scale * acc;
 }
 
+// ---------------------------------------------------------------------------
+// SIRT forward projection by ray tiles: 64 rays of consecutive bins at one
+// angle (lane = bin).  A ray whose direction is closer to the image columns
+// (|cos| > |sin|) crosses each image row at one or two adjacent pixels, one
+// closer to the rows crosses each column so; the layout stores, per step
+// (row, or column) and ray, the lower column (or row) index and the two
+// lengths, zero where absent: element (t, step, lane) at (t N + step) 64 +
+// lane, with each tile's used step range [s_lo, s_hi].  At a step the 64
+// rays read consecutive words and gather image values from one image row
+// (or, through the transposed image, one column) about 64-90 pixels wide.
+// Ray-major entries come by ascending row, then column, so the first entry
+// of a step is the lower pixel.  A step crossing holds at most two pixels
+// (the ray moves less than one pixel sideways per step); should rounding
+// give a corner-touching third one, or two that are not neighbours, the
+// tile is marked irregular (hi = -2) and its rays are summed from the CSR.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool ray_cols(const double* trig, int u)
+{
+    return fabs(trig[2 * u]) > fabs(trig[2 * u + 1]);
+}
+
+template <typename LenT>
+__global__ __launch_bounds__(64) void ray_tile_build_kernel(int N, int U, int K, int nkt,
+                                                           const double* __restrict__ trig,
+                                                           const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const LenT* __restrict__ ln,
+                                                           int32_t* __restrict__ tk, LenT* __restrict__ t0,
+                                                           LenT* __restrict__ t1,
+                                                           int32_t* __restrict__ range)
+{
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int u = t / nkt, k = (t - u * nkt) * 64 + lane;
+    const bool cols = ray_cols(trig, u);
+    const int64_t base = (int64_t)t * N * 64 + lane;
+    for (int st = 0; st < N; ++st) {
+        tk[base + (int64_t)st * 64] = -1;
+        t0[base + (int64_t)st * 64] = (LenT)0;
+        t1[base + (int64_t)st * 64] = (LenT)0;
+    }
+    int lo = N, hi = -1;
+    bool odd = false;
+    if (k < K) {
+        const int64_t g = (int64_t)u * K + k;
+        for (int64_t q = rp[g]; q < rp[g + 1]; ++q) {
+            const int p = ci[q];
+            const int i = p / N, j = p - i * N;
+            const int st = cols ? i : j, idx = cols ? j : i;
+            const int64_t at = base + (int64_t)st * 64;
+            if (tk[at] < 0) {
+                tk[at] = idx;
+                t0[at] = ln[q];
+            } else if (idx == tk[at] + 1 && t1[at] == (LenT)0) {
+                t1[at] = ln[q];
+            } else {
+                odd = true;
+            }
+            lo = st < lo ? st : lo;
+            hi = st > hi ? st : hi;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o, 64));
+        hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    odd = __any(odd);
+    if (lane == 0) {
+        range[2 * t] = odd ? 0 : lo;
+        range[2 * t + 1] = odd ? -2 : hi;
+    }
+}
+
+// res = Pm - A f per ray, q = res / W (0 where W = 0), and per-block sums of res^2
+template <typename LenT>
+__global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, int nkt, int n_tiles,
+                                                          const double* __restrict__ trig,
+                                                          const int32_t* __restrict__ tk,
+                                                          const LenT* __restrict__ t0,
+                                                          const LenT* __restrict__ t1,
+                                                          const int32_t* __restrict__ range,
+                                                          const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const LenT* __restrict__ ln,
+                                                          const double* __restrict__ f,
+                                                          const double* __restrict__ fT,
+                                                          const double* __restrict__ sino,
+                                                          const double* __restrict__ W,
+                                                          double* __restrict__ out,
+                                                          double* __restrict__ partial)
+{
+    constexpr int kS = 8;  // steps in flight
+    __shared__ double wpart[kWPB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double sq = 0.0;
+    const XcdRows xr = xcd_rows(n_tiles, w);
+    for (int64_t t = xr.first; t < xr.end; t += xr.stride) {
+        const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
+        const double* img = ray_cols(trig, u) ? f : fT;
+        const int lo = range[2 * t], hi = range[2 * t + 1];
+        const int64_t base = t * N * 64 + lane;
+        double acc = 0.0;
+        if (hi == -2 && k < K) {  // irregular tile: each lane walks its ray's entries
+            const int64_t g = (int64_t)u * K + k;
+            for (int64_t q = rp[g]; q < rp[g + 1]; ++q) acc = fma((double)ln[q], f[ci[q]], acc);
+        }
+        for (int s0 = lo; s0 <= hi; s0 += kS) {
+            int32_t ii[kS];
+            double a0[kS], a1[kS], v0[kS], v1[kS];
+#pragma unroll
+            for (int a = 0; a < kS; ++a) {
+                const int st = s0 + a <= hi ? s0 + a : hi;
+                ii[a] = tk[base + (int64_t)st * 64];
+                a0[a] = (double)t0[base + (int64_t)st * 64];
+                a1[a] = (double)t1[base + (int64_t)st * 64];
+            }
+#pragma unroll
+            for (int a = 0; a < kS; ++a) {
+                const int st = s0 + a <= hi ? s0 + a : hi;
+                const int i0 = ii[a] < 0 ? 0 : ii[a];
+                const int64_t at = (int64_t)st * N + i0;
+                v0[a] = img[at];
+                v1[a] = img[i0 + 1 < N ? at + 1 : at];
+            }
+#pragma unroll
+            for (int a = 0; a < kS; ++a) {
+                if (s0 + a <= hi) {
+                    acc = fma(a0[a], v0[a], acc);
+                    acc = fma(a1[a], v1[a], acc);
+                }
+            }
+        }
+        if (k < K) {
+            const int64_t g = (int64_t)u * K + k;
+            const double res = sino[g] - acc;
+            const double wg = W[g];
+            out[g] = wg > 0.0 ? res / wg : 0.0;
+            sq += res * res;
+        }
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) wpart[w] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < kWPB; ++q) s += wpart[q];
+        partial[blockIdx.x] = s;
+    }
+}
+
 // 8 x 8 tiles holding at least one support pixel, as (tile row << 16 | tile column)
 std::vector<int32_t> support_tiles(const pila_geom* g)
 {
@@ -340,7 +489,7 @@ std::vector<int32_t> support_tiles(const pila_geom* g)
 // SIRT workspace: factor matrix, scaled residual, block partials, costs,
 // the transposed image and the tile layout
 struct SirtLayout {
-    size_t W, q, partial, sse, fT, tiles, tk, t0, t1, total;
+    size_t W, q, partial, sse, fT, tiles, tk, t0, t1, rk, r0, r1, range, total;
 };
 
 SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
@@ -364,6 +513,12 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     L.tk = take(sizeof(int32_t) * cells);
     L.t0 = take(ls * cells);
     L.t1 = take(ls * cells);
+    const size_t nrt = (size_t)g->n_angles * ((g->n_bins + 63) / 64);
+    const size_t rcells = nrt * (size_t)g->n * 64;
+    L.rk = take(sizeof(int32_t) * rcells);
+    L.r0 = take(ls * rcells);
+    L.r1 = take(ls * rcells);
+    L.range = take(sizeof(int32_t) * 2 * nrt);
     L.total = at;
     return L;
 }
@@ -468,14 +623,22 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
         tile_build_kernel<LenT><<<n_tiles, 64, 0, st>>>(N, U, K, d_tiles, csr->row_ptr, csr->col,
                                                         (const LenT*)csr->len, tk, t0, t1);
     }
+    const int nkt = (K + 63) / 64, n_rt = U * nkt;
+    int32_t* rk = (int32_t*)(ws + L.rk);
+    LenT* r0 = (LenT*)(ws + L.r0);
+    LenT* r1 = (LenT*)(ws + L.r1);
+    int32_t* range = (int32_t*)(ws + L.range);
+    ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
+                                                     (const LenT*)csr->t_len, rk, r0, r1, range);
+    const unsigned rtb = gather_blocks(n_rt);
     const double scale = prm->lambda / (double)geom->n_angles;
     const dim3 tgrid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32));
     for (int32_t it = 0; it < prm->n_iter; ++it) {
         transpose_kernel<<<tgrid, 256, 0, st>>>(N, d_image, fT);
-        ray_gather_kernel<LenT, kResW><<<gb, 256, 0, st>>>(G, csr->t_row_ptr, csr->t_col,
-                                                           (const LenT*)csr->t_len, d_image, d_sino,
-                                                           W, q, partial, fT, csr->trig, N, K);
-        reduce_kernel<<<1, 256, 0, st>>>(partial, (int)gb, sse + it);
+        ray_tile_res_kernel<LenT><<<rtb, 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, rk, r0, r1, range,
+                                                      csr->t_row_ptr, csr->t_col, (const LenT*)csr->t_len,
+                                                      d_image, fT, d_sino, W, q, partial);
+        reduce_kernel<<<1, 256, 0, st>>>(partial, (int)rtb, sse + it);
         if (n_tiles > 0)
             tile_back_kernel<LenT><<<(unsigned)((n_tiles + kWPB - 1) / kWPB), 256, 0, st>>>(
                 N, U, K, n_tiles, d_tiles, csr->row_ptr, tk, t0, t1, q, d_image, scale);

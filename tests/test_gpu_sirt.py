@@ -18,11 +18,15 @@ def P():
     return P
 
 
-@pytest.mark.parametrize("N,U,K,lam,iters", [(32, 30, 46, 0.1, 20), (64, 90, 91, 1.0, 10),
-                                             (47, 33, 67, 0.5, 15)])
-def test_sirt_matches_oracle(P, N, U, K, lam, iters):
+# 4 and 12 angles include 45 and 135 degrees, where a ray's steps through
+# the image can touch pixel corners; 70 bins span two ray tiles of 64 with a
+# ragged tail
+@pytest.mark.parametrize("N,U,K,lam,iters,masked", [(32, 30, 46, 0.1, 20, True), (64, 90, 91, 1.0, 10, True),
+                                                    (47, 33, 67, 0.5, 15, True), (40, 4, 57, 0.5, 10, False),
+                                                    (33, 12, 70, 0.5, 12, False), (50, 12, 70, 0.3, 8, True)])
+def test_sirt_matches_oracle(P, N, U, K, lam, iters, masked):
     ell = datagen.random_ellipses(N + U, N, 6)
-    sl = datagen.make_slice(N, U, K, ell, masked=True, I0=1e4, noise_seed=5)
+    sl = datagen.make_slice(N, U, K, ell, masked=masked, I0=1e4, noise_seed=5)
     geom = P.Geometry(N, sl.angles, K, sl.mask, "f64")
     pl = P.pila_build(geom)
     img = torch.from_numpy(sl.f0.copy()).cuda()
