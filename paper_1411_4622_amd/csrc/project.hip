@@ -9,7 +9,9 @@
 // are deterministic and need no atomics.  Both stream the PILA from HBM
 // once per call (the image / sinogram being gathered stays in L2 / MALL):
 // these are HBM-bound kernels.
+#include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.hpp"
@@ -222,17 +224,31 @@ __global__ __launch_bounds__(256) void pixel_gather_kernel(int64_t NP, const int
 }
 
 // ---------------------------------------------------------------------------
-// SIRT back projection by pixel tiles.  The PILA row of a pixel holds, per
-// angle, one or two rays of adjacent bins (a unit pixel's shadow is at most
-// sqrt 2 bins wide).  For a tile of 8 x 8 pixels the tile layout stores, per
-// angle and pixel, the lower bin k and the lengths l0 (bin k) and l1 (bin
-// k + 1), zero where absent, angle-major: element (t, u, lane) at
-// (t U + u) 64 + lane.  A wavefront takes a tile (lane = pixel); at angle u
-// its 64 pixels read 64 consecutive words and gather sinogram values from a
-// span of about 12 bins of one sinogram row.  Each pixel adds its terms in
-// the row's order (angle, then bin), as a sequential walk of the row would.
+// Tile layouts for SIRT.  Both projections run one wavefront per tile of 64
+// PILA rows (lane = row) and walk the tile's rows in step: at one step each
+// lane holds at most two entries, at neighbouring indices, stored as an
+// 8-bit offset from the step's smallest index (one base per step) and two
+// lengths, zero where absent.  Element (t, s, lane) sits at (t S + s) 64 +
+// lane, so the 64 lanes of a step read consecutive bytes and words.  A tile
+// whose rows break that shape (a third entry at one step, a pair that is
+// not neighbours, an offset above 255) is flagged and its rows are summed
+// straight from the CSR.
+//
+// Back projection: tiles of 8 x 8 pixels, steps = angles.  A pixel's shadow
+// on the detector is at most sqrt 2 bins wide, so at one angle it meets one
+// or two rays of neighbouring bins, and the tile's 64 pixels meet about 12
+// bins of one sinogram row.  Each pixel adds its terms in its row's order
+// (angle, then bin), as a walk of the row would.
+//
+// Forward projection: tiles of 64 rays of consecutive bins at one angle;
+// steps are image rows for rays closer to the columns (|cos| > |sin|), image
+// columns for the others.  Such a ray moves less than one pixel sideways per
+// step, so it meets one or two neighbouring pixels there, and the tile's 64
+// rays meet about 64-91 pixels of one image row (read from the image) or
+// column (read from its transpose).  Steps run over the tile's used range.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 8;
+constexpr int kOdd = -2;  // flag of a tile summed from its CSR rows
 
 __device__ __forceinline__ int64_t tile_pixel(const int32_t* tiles, int t, int lane, int N)
 {
@@ -242,45 +258,267 @@ __device__ __forceinline__ int64_t tile_pixel(const int32_t* tiles, int t, int l
     return (i < N && j < N) ? (int64_t)i * N + j : -1;
 }
 
+__device__ __forceinline__ bool ray_cols(const double* trig, int u)
+{
+    return fabs(trig[2 * u]) > fabs(trig[2 * u + 1]);
+}
+
+// A lane's window of kWin consecutive PILA entries (index and length) in
+// LDS, aligned to kWin entries.  A tile build walks 64 rows at once, one per
+// lane, a few entries per step; read straight from memory each entry would
+// cost a cache line that is evicted again before the lane's next step.
+// Through the window each 64-byte segment is fetched once.
+constexpr int kWin = 16;
+
+template <typename LenT>
+struct EntryWindow {
+    int32_t* wc;  // LDS, kWin indices of this lane
+    LenT* wl;     // LDS, kWin lengths
+    int64_t w;    // first entry held
+    const int32_t* __restrict__ ci;
+    const LenT* __restrict__ ln;
+    int64_t nnz;
+    bool vec;  // ci and ln 16-byte aligned: fill with 16-byte loads
+    __device__ void fill(int64_t q)
+    {
+        w = q & ~(int64_t)(kWin - 1);
+        if (vec && w + kWin <= nnz) {
+            const int4* c4 = reinterpret_cast<const int4*>(ci + w);
+#pragma unroll
+            for (int a = 0; a < kWin / 4; ++a) {
+                const int4 v = c4[a];
+                wc[4 * a] = v.x;
+                wc[4 * a + 1] = v.y;
+                wc[4 * a + 2] = v.z;
+                wc[4 * a + 3] = v.w;
+            }
+            constexpr int kPer = 16 / (int)sizeof(LenT);
+            const int4* l4 = reinterpret_cast<const int4*>(ln + w);
+#pragma unroll
+            for (int a = 0; a < kWin / kPer; ++a) {
+                const int4 v = l4[a];
+                __builtin_memcpy(wl + a * kPer, &v, 16);
+            }
+        } else {
+            for (int a = 0; a < kWin && w + a < nnz; ++a) {
+                wc[a] = ci[w + a];
+                wl[a] = ln[w + a];
+            }
+        }
+    }
+    __device__ int32_t col(int64_t q)
+    {
+        if (q < w || q >= w + kWin) fill(q);
+        return wc[q - w];
+    }
+    __device__ LenT len(int64_t q)
+    {
+        if (q < w || q >= w + kWin) fill(q);
+        return wl[q - w];
+    }
+};
+
+// LDS of the 64 lanes' windows (rows padded by one word against bank conflicts)
+template <typename LenT>
+struct WindowLds {
+    int32_t c[64][kWin + 1];
+    LenT l[64][kWin + 1];
+};
+
+template <typename LenT>
+__device__ __forceinline__ EntryWindow<LenT> entry_window(WindowLds<LenT>& lds, int lane,
+                                                          const int32_t* ci, const LenT* ln,
+                                                          int64_t nnz, bool vec)
+{
+    return EntryWindow<LenT>{lds.c[lane], lds.l[lane], -(int64_t)kWin - 1, ci, ln, nnz, vec};
+}
+
+// Walk of a PILA row in its stored order.
+struct RowWalk {
+    int64_t q, e;
+    __device__ bool more() const { return q < e; }
+    template <typename Win>
+    __device__ void next(Win&) { ++q; }
+};
+
+// Walk of a ray's entries in ascending step order.  Entries are stored by
+// ascending image row, then column.  Where the steps are image rows, or are
+// columns that rise with the rows, that order already is the step order;
+// for a ray whose columns fall as its rows rise, the walk takes the row
+// groups (entries of one image row) last to first, each first to last.
+struct RayWalk {
+    int N;
+    int64_t b, q, gs, ge;
+    bool rev;
+    template <typename Win>
+    __device__ int64_t group_start(Win& win, int64_t x) const
+    {
+        const int r = win.col(x) / N;
+        while (x > b && win.col(x - 1) / N == r) --x;
+        return x;
+    }
+    template <typename Win>
+    __device__ RayWalk(Win& win, int n, int64_t b0, int64_t e0, bool reverse)
+        : N(n), b(b0), q(b0), gs(b0), ge(e0), rev(reverse && e0 > b0)
+    {
+        if (rev) q = gs = group_start(win, e0 - 1);
+    }
+    __device__ bool more() const { return q < ge; }
+    template <typename Win>
+    __device__ void next(Win& win)
+    {
+        if (++q == ge && rev && gs > b) {
+            ge = gs;
+            gs = group_start(win, gs - 1);
+            q = gs;
+        }
+    }
+};
+
+// One step of a tile build: each lane takes the entries of its row at step
+// st from its walk, and the wave writes the step's cells and base.  False
+// where the entries break the tile shape.  Every lane of the wavefront calls
+// it with the same st.
+template <typename LenT, typename Walk, typename Key>
+__device__ __forceinline__ bool tile_step(int st, int R, Walk& wk, EntryWindow<LenT>& win, const Key& key,
+                                          int64_t cell, int64_t bcell, uint8_t* __restrict__ off,
+                                          LenT* __restrict__ l0, LenT* __restrict__ l1,
+                                          int32_t* __restrict__ base)
+{
+    int ia = -1, ib = -1;
+    LenT la = (LenT)0, lb = (LenT)0;
+    bool ok = true;
+    for (int c = 0; c < 3 && wk.more(); ++c) {
+        int s, idx;
+        key(win.col(wk.q), &s, &idx);
+        if (s != st) break;
+        if (c == 0) {
+            ia = idx;
+            la = win.len(wk.q);
+        } else if (c == 1) {
+            ib = idx;
+            lb = win.len(wk.q);
+        } else {
+            ok = false;
+        }
+        wk.next(win);
+    }
+    if (ib >= 0 && ib < ia) {
+        const int ti = ia;
+        ia = ib;
+        ib = ti;
+        const LenT tl = la;
+        la = lb;
+        lb = tl;
+    }
+    if (ib >= 0 && ib != ia + 1) ok = false;
+    if (ia >= R || (ia < 0 && ib >= 0)) {  // not an index of this step's line
+        ok = false;
+        ia = ib = -1;
+    }
+    int m = ia >= 0 ? ia : INT_MAX;
+    for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_xor(m, o, 64));
+    const int d = ia >= 0 ? ia - m : 0;
+    if (d > 255) ok = false;
+    off[cell] = (uint8_t)(d > 255 ? 0 : d);
+    l0[cell] = la;
+    l1[cell] = lb;
+    if ((threadIdx.x & 63) == 0) base[bcell] = m == INT_MAX ? 0 : m;
+    return ok;
+}
+
+// Sum over the steps lo..hi of one lane's tile cells: l0 src[s R + x] +
+// l1 src[s R + x + 1] with x = base[s] + offset, S steps at a time.  The
+// next group's cells are loaded after this group's gathers are issued, so
+// they are in flight while the gathers are waited for (loads complete in
+// issue order).  Terms are added by ascending step, l0 before l1.
+template <typename LenT, int S>
+__device__ __forceinline__ double tile_sum(int lo, int hi, int R, const int32_t* __restrict__ tb,
+                                           const uint8_t* __restrict__ off, const LenT* __restrict__ l0,
+                                           const LenT* __restrict__ l1, int64_t cb,
+                                           const double* __restrict__ src)
+{
+    double acc = 0.0;
+    if (lo > hi) return acc;
+    int32_t ii[S];
+    LenT a0[S], a1[S];
+    auto load = [&](int s0) {
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+            const int st = s0 + a <= hi ? s0 + a : hi;
+            ii[a] = tb[st] + (int32_t)off[cb + (int64_t)st * 64];
+            a0[a] = l0[cb + (int64_t)st * 64];
+            a1[a] = l1[cb + (int64_t)st * 64];
+        }
+    };
+    load(lo);
+    for (int s0 = lo; s0 <= hi; s0 += S) {
+        double v0[S], v1[S];
+        LenT c0[S], c1[S];
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+            const int st = s0 + a <= hi ? s0 + a : hi;
+            const int64_t at = (int64_t)st * R + ii[a];
+            v0[a] = src[at];
+            v1[a] = src[ii[a] + 1 < R ? at + 1 : at];
+            c0[a] = a0[a];
+            c1[a] = a1[a];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (s0 + S <= hi) load(s0 + S);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+            if (s0 + a <= hi) {
+                acc = fma((double)c0[a], v0[a], acc);
+                acc = fma((double)c1[a], v1[a], acc);
+            }
+        }
+    }
+    return acc;
+}
+
 template <typename LenT>
 __global__ __launch_bounds__(64) void tile_build_kernel(int N, int U, int K, const int32_t* __restrict__ tiles,
                                                        const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci,
                                                        const LenT* __restrict__ ln,
-                                                       int32_t* __restrict__ tk, LenT* __restrict__ t0,
-                                                       LenT* __restrict__ t1)
+                                                       uint8_t* __restrict__ off, LenT* __restrict__ l0,
+                                                       LenT* __restrict__ l1, int32_t* __restrict__ base,
+                                                       int32_t* __restrict__ flag, int64_t nnz, bool vec,
+                                                       bool force_csr)
 {
+    __shared__ WindowLds<LenT> lds;
     const int t = blockIdx.x, lane = threadIdx.x;
-    const int64_t base = (int64_t)t * U * 64;
-    for (int u = 0; u < U; ++u) {
-        tk[base + (int64_t)u * 64 + lane] = 0;
-        t0[base + (int64_t)u * 64 + lane] = (LenT)0;
-        t1[base + (int64_t)u * 64 + lane] = (LenT)0;
-    }
     const int64_t p = tile_pixel(tiles, t, lane, N);
-    if (p < 0) return;
-    int prev = -1;
-    for (int64_t q = rp[p]; q < rp[p + 1]; ++q) {
-        const int g = ci[q];
-        const int u = g / K, k = g - u * K;
-        const int64_t at = base + (int64_t)u * 64 + lane;
-        if (u == prev) {
-            t1[at] = ln[q];
-        } else {
-            tk[at] = k;
-            t0[at] = ln[q];
-            prev = u;
-        }
+    auto key = [&](int g, int* s, int* idx) {
+        const int u = g / K;
+        *s = u;
+        *idx = g - u * K;
+    };
+    EntryWindow<LenT> win = entry_window(lds, lane, ci, ln, nnz, vec);
+    RowWalk wk{p >= 0 ? rp[p] : 0, p >= 0 ? rp[p + 1] : 0};
+    bool ok = true;
+    for (int u = 0; u < U; ++u) {
+        const int64_t bc = (int64_t)t * U + u;
+        ok &= tile_step<LenT>(u, K, wk, win, key, bc * 64 + lane, bc, off, l0, l1, base);
     }
+    if (wk.more() || force_csr) ok = false;
+    const bool odd = __any(!ok);
+    if (lane == 0) flag[t] = odd ? kOdd : 0;
 }
 
 template <typename LenT>
 __global__ __launch_bounds__(256) void tile_back_kernel(int N, int U, int K, int n_tiles,
                                                        const int32_t* __restrict__ tiles,
                                                        const int64_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ tk,
-                                                       const LenT* __restrict__ t0,
-                                                       const LenT* __restrict__ t1,
+                                                       const int32_t* __restrict__ ci,
+                                                       const LenT* __restrict__ ln,
+                                                       const int32_t* __restrict__ flag,
+                                                       const uint8_t* __restrict__ off,
+                                                       const LenT* __restrict__ l0,
+                                                       const LenT* __restrict__ l1,
+                                                       const int32_t* __restrict__ base,
                                                        const double* __restrict__ y,
                                                        double* __restrict__ f, double scale)
 {
@@ -288,56 +526,16 @@ __global__ __launch_bounds__(256) void tile_back_kernel(int N, int U, int K, int
     const int lane = threadIdx.x & 63;
     const int t = blockIdx.x * kWPB + (threadIdx.x >> 6);
     if (t >= n_tiles) return;
-    const int64_t base = (int64_t)t * U * 64 + lane;
-    double acc = 0.0;
-    for (int u0 = 0; u0 < U; u0 += kA) {
-        int32_t kk[kA];
-        double a0[kA], a1[kA], y0[kA], y1[kA];
-#pragma unroll
-        for (int a = 0; a < kA; ++a) {
-            const int u = u0 + a < U ? u0 + a : U - 1;
-            kk[a] = tk[base + (int64_t)u * 64];
-            a0[a] = (double)t0[base + (int64_t)u * 64];
-            a1[a] = (double)t1[base + (int64_t)u * 64];
-        }
-#pragma unroll
-        for (int a = 0; a < kA; ++a) {
-            const int u = u0 + a < U ? u0 + a : U - 1;
-            const int64_t g = (int64_t)u * K + kk[a];
-            y0[a] = y[g];
-            y1[a] = y[kk[a] + 1 < K ? g + 1 : g];
-        }
-#pragma unroll
-        for (int a = 0; a < kA; ++a) {
-            if (u0 + a < U) {
-                acc = fma(a0[a], y0[a], acc);
-                acc = fma(a1[a], y1[a], acc);
-            }
-        }
-    }
     const int64_t p = tile_pixel(tiles, t, lane, N);
+    double acc = 0.0;
+    if (flag[t] == kOdd) {
+        if (p >= 0)
+            for (int64_t q = rp[p]; q < rp[p + 1]; ++q) acc = fma((double)ln[q], y[ci[q]], acc);
+    } else {
+        const int64_t cb = (int64_t)t * U * 64 + lane;
+        acc = tile_sum<LenT, kA>(0, U - 1, K, base + (int64_t)t * U, off, l0, l1, cb, y);
+    }
     if (p >= 0 && rp[p + 1] > rp[p]) f[p] = f[p] + scale * acc;
-}
-
-// ---------------------------------------------------------------------------
-// SIRT forward projection by ray tiles: 64 rays of consecutive bins at one
-// angle (lane = bin).  A ray whose direction is closer to the image columns
-// (|cos| > |sin|) crosses each image row at one or two adjacent pixels, one
-// closer to the rows crosses each column so; the layout stores, per step
-// (row, or column) and ray, the lower column (or row) index and the two
-// lengths, zero where absent: element (t, step, lane) at (t N + step) 64 +
-// lane, with each tile's used step range [s_lo, s_hi].  At a step the 64
-// rays read consecutive words and gather image values from one image row
-// (or, through the transposed image, one column) about 64-90 pixels wide.
-// Ray-major entries come by ascending row, then column, so the first entry
-// of a step is the lower pixel.  A step crossing holds at most two pixels
-// (the ray moves less than one pixel sideways per step); should rounding
-// give a corner-touching third one, or two that are not neighbours, the
-// tile is marked irregular (hi = -2) and its rays are summed from the CSR.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool ray_cols(const double* trig, int u)
-{
-    return fabs(trig[2 * u]) > fabs(trig[2 * u + 1]);
 }
 
 template <typename LenT>
@@ -346,48 +544,52 @@ __global__ __launch_bounds__(64) void ray_tile_build_kernel(int N, int U, int K,
                                                            const int64_t* __restrict__ rp,
                                                            const int32_t* __restrict__ ci,
                                                            const LenT* __restrict__ ln,
-                                                           int32_t* __restrict__ tk, LenT* __restrict__ t0,
-                                                           LenT* __restrict__ t1,
-                                                           int32_t* __restrict__ range)
+                                                           uint8_t* __restrict__ off, LenT* __restrict__ l0,
+                                                           LenT* __restrict__ l1, int32_t* __restrict__ base,
+                                                           int32_t* __restrict__ range, int64_t nnz, bool vec,
+                                                           bool force_csr)
 {
+    __shared__ WindowLds<LenT> lds;
     const int t = blockIdx.x, lane = threadIdx.x;
     const int u = t / nkt, k = (t - u * nkt) * 64 + lane;
     const bool cols = ray_cols(trig, u);
-    const int64_t base = (int64_t)t * N * 64 + lane;
-    for (int st = 0; st < N; ++st) {
-        tk[base + (int64_t)st * 64] = -1;
-        t0[base + (int64_t)st * 64] = (LenT)0;
-        t1[base + (int64_t)st * 64] = (LenT)0;
-    }
+    auto key = [&](int p, int* s, int* idx) {
+        const int i = p / N, j = p - i * N;
+        *s = cols ? i : j;
+        *idx = cols ? j : i;
+    };
+    EntryWindow<LenT> win = entry_window(lds, lane, ci, ln, nnz, vec);
+    const int64_t g = (int64_t)u * K + k;
+    const int64_t b = k < K ? rp[g] : 0, e = k < K ? rp[g + 1] : 0;
     int lo = N, hi = -1;
-    bool odd = false;
-    if (k < K) {
-        const int64_t g = (int64_t)u * K + k;
-        for (int64_t q = rp[g]; q < rp[g + 1]; ++q) {
-            const int p = ci[q];
-            const int i = p / N, j = p - i * N;
-            const int st = cols ? i : j, idx = cols ? j : i;
-            const int64_t at = base + (int64_t)st * 64;
-            if (tk[at] < 0) {
-                tk[at] = idx;
-                t0[at] = ln[q];
-            } else if (idx == tk[at] + 1 && t1[at] == (LenT)0) {
-                t1[at] = ln[q];
-            } else {
-                odd = true;
-            }
-            lo = st < lo ? st : lo;
-            hi = st > hi ? st : hi;
+    bool bad = false;
+    for (int64_t q = b; q < e; ++q) {
+        int s, x;
+        key(win.col(q), &s, &x);
+        if (s < 0 || s >= N) {  // not a pixel index: the tile is summed from the CSR
+            bad = true;
+            continue;
         }
+        lo = min(lo, s);
+        hi = max(hi, s);
     }
     for (int o = 32; o > 0; o >>= 1) {
         lo = min(lo, __shfl_xor(lo, o, 64));
         hi = max(hi, __shfl_xor(hi, o, 64));
     }
-    odd = __any(odd);
+    // a row of the image is one pixel high, and the ray moves s / c pixels
+    // along it per row: its columns fall as its rows rise where c s < 0
+    RayWalk wk(win, N, b, e, !cols && trig[2 * u] * trig[2 * u + 1] < 0.0);
+    bool ok = true;
+    for (int st = lo; st <= hi; ++st) {
+        const int64_t bc = (int64_t)t * N + st;
+        ok &= tile_step<LenT>(st, N, wk, win, key, bc * 64 + lane, bc, off, l0, l1, base);
+    }
+    if (wk.more() || bad || force_csr) ok = false;
+    const bool odd = __any(!ok);
     if (lane == 0) {
         range[2 * t] = odd ? 0 : lo;
-        range[2 * t + 1] = odd ? -2 : hi;
+        range[2 * t + 1] = odd ? kOdd : hi;
     }
 }
 
@@ -395,9 +597,10 @@ __global__ __launch_bounds__(64) void ray_tile_build_kernel(int N, int U, int K,
 template <typename LenT>
 __global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, int nkt, int n_tiles,
                                                           const double* __restrict__ trig,
-                                                          const int32_t* __restrict__ tk,
-                                                          const LenT* __restrict__ t0,
-                                                          const LenT* __restrict__ t1,
+                                                          const uint8_t* __restrict__ off,
+                                                          const LenT* __restrict__ l0,
+                                                          const LenT* __restrict__ l1,
+                                                          const int32_t* __restrict__ base,
                                                           const int32_t* __restrict__ range,
                                                           const int64_t* __restrict__ rp,
                                                           const int32_t* __restrict__ ci,
@@ -418,38 +621,12 @@ __global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, 
         const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
         const double* img = ray_cols(trig, u) ? f : fT;
         const int lo = range[2 * t], hi = range[2 * t + 1];
-        const int64_t base = t * N * 64 + lane;
         double acc = 0.0;
-        if (hi == -2 && k < K) {  // irregular tile: each lane walks its ray's entries
+        if (hi == kOdd && k < K) {
             const int64_t g = (int64_t)u * K + k;
             for (int64_t q = rp[g]; q < rp[g + 1]; ++q) acc = fma((double)ln[q], f[ci[q]], acc);
         }
-        for (int s0 = lo; s0 <= hi; s0 += kS) {
-            int32_t ii[kS];
-            double a0[kS], a1[kS], v0[kS], v1[kS];
-#pragma unroll
-            for (int a = 0; a < kS; ++a) {
-                const int st = s0 + a <= hi ? s0 + a : hi;
-                ii[a] = tk[base + (int64_t)st * 64];
-                a0[a] = (double)t0[base + (int64_t)st * 64];
-                a1[a] = (double)t1[base + (int64_t)st * 64];
-            }
-#pragma unroll
-            for (int a = 0; a < kS; ++a) {
-                const int st = s0 + a <= hi ? s0 + a : hi;
-                const int i0 = ii[a] < 0 ? 0 : ii[a];
-                const int64_t at = (int64_t)st * N + i0;
-                v0[a] = img[at];
-                v1[a] = img[i0 + 1 < N ? at + 1 : at];
-            }
-#pragma unroll
-            for (int a = 0; a < kS; ++a) {
-                if (s0 + a <= hi) {
-                    acc = fma(a0[a], v0[a], acc);
-                    acc = fma(a1[a], v1[a], acc);
-                }
-            }
-        }
+        acc += tile_sum<LenT, kS>(lo, hi, N, base + t * N, off, l0, l1, t * N * 64 + lane, img);
         if (k < K) {
             const int64_t g = (int64_t)u * K + k;
             const double res = sino[g] - acc;
@@ -489,7 +666,7 @@ std::vector<int32_t> support_tiles(const pila_geom* g)
 // SIRT workspace: factor matrix, scaled residual, block partials, costs,
 // the transposed image and the tile layout
 struct SirtLayout {
-    size_t W, q, partial, sse, fT, tiles, tk, t0, t1, rk, r0, r1, range, total;
+    size_t W, q, partial, sse, fT, tiles, flag, off, l0, l1, base, roff, r0, r1, rbase, range, total;
 };
 
 SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
@@ -510,14 +687,17 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     L.sse = take(sizeof(double) * (size_t)(n_iter > 0 ? n_iter : 1));
     L.fT = take(sizeof(double) * NP);
     L.tiles = take(sizeof(int32_t) * (n_tiles ? n_tiles : 1));
-    L.tk = take(sizeof(int32_t) * cells);
-    L.t0 = take(ls * cells);
-    L.t1 = take(ls * cells);
+    L.flag = take(sizeof(int32_t) * (n_tiles ? n_tiles : 1));
+    L.off = take(cells);
+    L.l0 = take(ls * cells);
+    L.l1 = take(ls * cells);
+    L.base = take(sizeof(int32_t) * (cells / 64));
     const size_t nrt = (size_t)g->n_angles * ((g->n_bins + 63) / 64);
     const size_t rcells = nrt * (size_t)g->n * 64;
-    L.rk = take(sizeof(int32_t) * rcells);
+    L.roff = take(rcells);
     L.r0 = take(ls * rcells);
     L.r1 = take(ls * rcells);
+    L.rbase = take(sizeof(int32_t) * (rcells / 64));
     L.range = take(sizeof(int32_t) * 2 * nrt);
     L.total = at;
     return L;
@@ -593,6 +773,11 @@ extern "C" int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params*
     return PILA_OK;
 }
 
+static bool aligned16(const void* a, const void* b)
+{
+    return ((uintptr_t)a % 16) == 0 && ((uintptr_t)b % 16) == 0;
+}
+
 template <typename LenT>
 static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
                          const sirt_params* prm, double* d_image, char* ws, double* h_cost,
@@ -609,10 +794,16 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     double* sse = (double*)(ws + L.sse);
     double* fT = (double*)(ws + L.fT);
     int32_t* d_tiles = (int32_t*)(ws + L.tiles);
-    int32_t* tk = (int32_t*)(ws + L.tk);
-    LenT* t0 = (LenT*)(ws + L.t0);
-    LenT* t1 = (LenT*)(ws + L.t1);
+    int32_t* flag = (int32_t*)(ws + L.flag);
+    uint8_t* off = (uint8_t*)(ws + L.off);
+    LenT* l0 = (LenT*)(ws + L.l0);
+    LenT* l1 = (LenT*)(ws + L.l1);
+    int32_t* base = (int32_t*)(ws + L.base);
     const unsigned gb = gather_blocks(G);
+    // PILA_SIRT_CSR=1 sums every tile from its CSR rows (the path a tile of
+    // irregular shape takes), for tests of that path
+    const char* env = std::getenv("PILA_SIRT_CSR");
+    const bool force_csr = env && env[0] == '1';
     // factor matrix: W_g = sum of squared lengths of ray g over the support
     ray_gather_kernel<LenT, kW><<<gb, 256, 0, st>>>(G, csr->t_row_ptr, csr->t_col,
                                                     (const LenT*)csr->t_len, nullptr, nullptr,
@@ -621,27 +812,31 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
         PILA_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
                                 hipMemcpyHostToDevice, st));
         tile_build_kernel<LenT><<<n_tiles, 64, 0, st>>>(N, U, K, d_tiles, csr->row_ptr, csr->col,
-                                                        (const LenT*)csr->len, tk, t0, t1);
+                                                        (const LenT*)csr->len, off, l0, l1, base, flag,
+                                                        csr->nnz, aligned16(csr->col, csr->len), force_csr);
     }
     const int nkt = (K + 63) / 64, n_rt = U * nkt;
-    int32_t* rk = (int32_t*)(ws + L.rk);
+    uint8_t* roff = (uint8_t*)(ws + L.roff);
     LenT* r0 = (LenT*)(ws + L.r0);
     LenT* r1 = (LenT*)(ws + L.r1);
+    int32_t* rbase = (int32_t*)(ws + L.rbase);
     int32_t* range = (int32_t*)(ws + L.range);
     ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
-                                                     (const LenT*)csr->t_len, rk, r0, r1, range);
+                                                     (const LenT*)csr->t_len, roff, r0, r1, rbase, range,
+                                                     csr->nnz, aligned16(csr->t_col, csr->t_len), force_csr);
     const unsigned rtb = gather_blocks(n_rt);
     const double scale = prm->lambda / (double)geom->n_angles;
     const dim3 tgrid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32));
     for (int32_t it = 0; it < prm->n_iter; ++it) {
         transpose_kernel<<<tgrid, 256, 0, st>>>(N, d_image, fT);
-        ray_tile_res_kernel<LenT><<<rtb, 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, rk, r0, r1, range,
+        ray_tile_res_kernel<LenT><<<rtb, 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, roff, r0, r1, rbase, range,
                                                       csr->t_row_ptr, csr->t_col, (const LenT*)csr->t_len,
                                                       d_image, fT, d_sino, W, q, partial);
         reduce_kernel<<<1, 256, 0, st>>>(partial, (int)rtb, sse + it);
         if (n_tiles > 0)
             tile_back_kernel<LenT><<<(unsigned)((n_tiles + kWPB - 1) / kWPB), 256, 0, st>>>(
-                N, U, K, n_tiles, d_tiles, csr->row_ptr, tk, t0, t1, q, d_image, scale);
+                N, U, K, n_tiles, d_tiles, csr->row_ptr, csr->col, (const LenT*)csr->len, flag, off, l0, l1,
+                base, q, d_image, scale);
     }
     PILA_HIP(hipGetLastError());
     if (h_cost && prm->n_iter > 0) {
