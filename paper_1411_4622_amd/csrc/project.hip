@@ -508,6 +508,32 @@ __global__ __launch_bounds__(64) void tile_build_kernel(int N, int U, int K, con
     if (lane == 0) flag[t] = odd ? kOdd : 0;
 }
 
+// Workgroup b's tile: workgroups go to the 8 XCDs round robin, so XCD x
+// takes the x-th eighth of the tiles (neighbouring tiles, shared L2 lines);
+// -1 for the padding of the grid to a multiple of 8.
+__device__ __forceinline__ int64_t xcd_tile(int64_t n)
+{
+    constexpr int kXcd = 8;
+    const int64_t chunk = (n + kXcd - 1) / kXcd;
+    const int64_t t = (int64_t)(blockIdx.x % kXcd) * chunk + blockIdx.x / kXcd;
+    return (int64_t)(blockIdx.x / kXcd) < chunk && t < n ? t : -1;
+}
+
+unsigned xcd_grid(int64_t n)
+{
+    return (unsigned)(8 * ((n + 7) / 8));
+}
+
+// The steps lo..hi split in kWPB nearly equal parts, wavefront w taking part w
+__device__ __forceinline__ void wave_part(int lo, int hi, int w, int* a, int* b)
+{
+    const int64_t n = (int64_t)hi - lo + 1;
+    *a = lo + (int)(n * w / kWPB);
+    *b = lo + (int)(n * (w + 1) / kWPB) - 1;
+}
+
+// One workgroup per pixel tile; its 4 wavefronts take a quarter of the
+// angles each, and their sums are added in wavefront order.
 template <typename LenT>
 __global__ __launch_bounds__(256) void tile_back_kernel(int N, int U, int K, int n_tiles,
                                                        const int32_t* __restrict__ tiles,
@@ -523,19 +549,26 @@ __global__ __launch_bounds__(256) void tile_back_kernel(int N, int U, int K, int
                                                        double* __restrict__ f, double scale)
 {
     constexpr int kA = 8;  // angles in flight
-    const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWPB + (threadIdx.x >> 6);
-    if (t >= n_tiles) return;
-    const int64_t p = tile_pixel(tiles, t, lane, N);
+    __shared__ double part[kWPB][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t t = xcd_tile(n_tiles);
+    if (t < 0) return;
+    const int64_t p = tile_pixel(tiles, (int)t, lane, N);
     double acc = 0.0;
     if (flag[t] == kOdd) {
-        if (p >= 0)
+        if (w == 0 && p >= 0)
             for (int64_t q = rp[p]; q < rp[p + 1]; ++q) acc = fma((double)ln[q], y[ci[q]], acc);
     } else {
-        const int64_t cb = (int64_t)t * U * 64 + lane;
-        acc = tile_sum<LenT, kA>(0, U - 1, K, base + (int64_t)t * U, off, l0, l1, cb, y);
+        int a, b;
+        wave_part(0, U - 1, w, &a, &b);
+        acc = tile_sum<LenT, kA>(a, b, K, base + t * U, off, l0, l1, t * U * 64 + lane, y);
     }
-    if (p >= 0 && rp[p + 1] > rp[p]) f[p] = f[p] + scale * acc;
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+        const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        if (p >= 0 && rp[p + 1] > rp[p]) f[p] = f[p] + scale * sum;
+    }
 }
 
 template <typename LenT>
@@ -593,7 +626,9 @@ __global__ __launch_bounds__(64) void ray_tile_build_kernel(int N, int U, int K,
     }
 }
 
-// res = Pm - A f per ray, q = res / W (0 where W = 0), and per-block sums of res^2
+// res = Pm - A f per ray, q = res / W (0 where W = 0), and per ray tile the
+// sum of res^2.  One workgroup per ray tile; its 4 wavefronts take a quarter
+// of the tile's steps each, and their sums are added in wavefront order.
 template <typename LenT>
 __global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, int nkt, int n_tiles,
                                                           const double* __restrict__ trig,
@@ -613,35 +648,38 @@ __global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, 
                                                           double* __restrict__ partial)
 {
     constexpr int kS = 8;  // steps in flight
-    __shared__ double wpart[kWPB];
+    __shared__ double part[kWPB][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double sq = 0.0;
-    const XcdRows xr = xcd_rows(n_tiles, w);
-    for (int64_t t = xr.first; t < xr.end; t += xr.stride) {
-        const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
-        const double* img = ray_cols(trig, u) ? f : fT;
-        const int lo = range[2 * t], hi = range[2 * t + 1];
-        double acc = 0.0;
-        if (hi == kOdd && k < K) {
+    const int64_t t = xcd_tile(n_tiles);
+    if (t < 0) return;
+    const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
+    const double* img = ray_cols(trig, u) ? f : fT;
+    const int lo = range[2 * t], hi = range[2 * t + 1];
+    double acc = 0.0;
+    if (hi == kOdd) {
+        if (w == 0 && k < K) {
             const int64_t g = (int64_t)u * K + k;
             for (int64_t q = rp[g]; q < rp[g + 1]; ++q) acc = fma((double)ln[q], f[ci[q]], acc);
         }
-        acc += tile_sum<LenT, kS>(lo, hi, N, base + t * N, off, l0, l1, t * N * 64 + lane, img);
+    } else if (lo <= hi) {
+        int a, b;
+        wave_part(lo, hi, w, &a, &b);
+        acc = tile_sum<LenT, kS>(a, b, N, base + t * N, off, l0, l1, t * N * 64 + lane, img);
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0) {
+        const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        double sq = 0.0;
         if (k < K) {
             const int64_t g = (int64_t)u * K + k;
-            const double res = sino[g] - acc;
+            const double res = sino[g] - sum;
             const double wg = W[g];
             out[g] = wg > 0.0 ? res / wg : 0.0;
-            sq += res * res;
+            sq = res * res;
         }
-    }
-    sq = wave_sum(sq);
-    if (lane == 0) wpart[w] = sq;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int q = 0; q < kWPB; ++q) s += wpart[q];
-        partial[blockIdx.x] = s;
+        sq = wave_sum(sq);
+        if (lane == 0) partial[t] = sq;
     }
 }
 
@@ -683,7 +721,8 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     };
     L.W = take(sizeof(double) * G);
     L.q = take(sizeof(double) * G);
-    L.partial = take(sizeof(double) * kGatherBlocks);
+    const size_t nrt0 = (size_t)g->n_angles * ((g->n_bins + 63) / 64);
+    L.partial = take(sizeof(double) * (nrt0 > (size_t)kGatherBlocks ? nrt0 : (size_t)kGatherBlocks));
     L.sse = take(sizeof(double) * (size_t)(n_iter > 0 ? n_iter : 1));
     L.fT = take(sizeof(double) * NP);
     L.tiles = take(sizeof(int32_t) * (n_tiles ? n_tiles : 1));
@@ -824,17 +863,17 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
                                                      (const LenT*)csr->t_len, roff, r0, r1, rbase, range,
                                                      csr->nnz, aligned16(csr->t_col, csr->t_len), force_csr);
-    const unsigned rtb = gather_blocks(n_rt);
+
     const double scale = prm->lambda / (double)geom->n_angles;
     const dim3 tgrid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32));
     for (int32_t it = 0; it < prm->n_iter; ++it) {
         transpose_kernel<<<tgrid, 256, 0, st>>>(N, d_image, fT);
-        ray_tile_res_kernel<LenT><<<rtb, 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, roff, r0, r1, rbase, range,
+        ray_tile_res_kernel<LenT><<<xcd_grid(n_rt), 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, roff, r0, r1, rbase, range,
                                                       csr->t_row_ptr, csr->t_col, (const LenT*)csr->t_len,
                                                       d_image, fT, d_sino, W, q, partial);
-        reduce_kernel<<<1, 256, 0, st>>>(partial, (int)rtb, sse + it);
+        reduce_kernel<<<1, 256, 0, st>>>(partial, n_rt, sse + it);
         if (n_tiles > 0)
-            tile_back_kernel<LenT><<<(unsigned)((n_tiles + kWPB - 1) / kWPB), 256, 0, st>>>(
+            tile_back_kernel<LenT><<<xcd_grid(n_tiles), 256, 0, st>>>(
                 N, U, K, n_tiles, d_tiles, csr->row_ptr, csr->col, (const LenT*)csr->len, flag, off, l0, l1,
                 base, q, d_image, scale);
     }
