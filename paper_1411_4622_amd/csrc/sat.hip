@@ -687,6 +687,17 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         J.UL = 0;
         simple_ids.push_back(j);
     }
+    // longest chains first (estimated work: steps x estimates x mean row
+    // length), so that no long chain starts late behind short ones and sets
+    // the batch's makespan; results do not depend on the order
+    auto work = [&](int j) {
+        const double row = jobs[j].csr->n_support > 0
+                               ? (double)jobs[j].csr->nnz / (double)jobs[j].csr->n_support
+                               : 1.0;
+        return (double)jobs[j].params.n_steps * (double)jobs[j].params.m_cand * (row + 8.0);
+    };
+    for (std::vector<int>* ids : {&piped_ids, &long_ids, &simple_ids})
+        std::stable_sort(ids->begin(), ids->end(), [&](int a, int b) { return work(a) > work(b); });
     std::vector<int> order(piped_ids);
     order.insert(order.end(), long_ids.begin(), long_ids.end());
     order.insert(order.end(), simple_ids.begin(), simple_ids.end());
