@@ -236,12 +236,27 @@ def run_c4(args, P, torch, datagen):
         e1.synchronize()
         sat_s = e0.elapsed_time(e1) / 1e3
         rm_sat = datagen.rmse(img.cpu().numpy(), sl.truth)
+    # the same chain in FP64 (FP64 PILA, same seeds) for the RMSE ratio
+    rm64, sat64_s = float("nan"), float("nan")
+    if steps > 0 and not getattr(args, "no_fp64_reference", False):
+        pl64 = P.pila_build(P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f64"))
+        prm64 = _params(P, cfg, steps, cfg["chain_seed"], 0, "f64")
+        img.copy_(f0)
+        e0.record()
+        P.sat_run(pl64, sino, prm64, img)
+        e1.record()
+        e1.synchronize()
+        sat64_s = e0.elapsed_time(e1) / 1e3
+        rm64 = datagen.rmse(img.cpu().numpy(), sl.truth)
+        del pl64
+        log("c4: FP64 chain in %.1f s" % sat64_s)
     out = {
         "workload": "c4", "N": sl.N, "U": sl.U, "K": sl.K, "nnz": pl.nnz, "max_row": pl.max_row,
         "pila_build_s": build_s,
         "sirt": {"iterations": n_it, "lambda": lam, "seconds": sirt_s, "ms_per_iteration":
                  1e3 * sirt_s / n_it, "rmse": rm_sirt,
-                 "roofline": {"kernel": "ray_gather_kernel + pixel_gather_kernel", "bound": "hbm",
+                 "roofline": {"kernel": "ray_tile_part_kernel + tile_back_kernel (whole iteration)",
+                              "bound": "hbm",
                               "achieved": sirt_bytes / sirt_s / 1e9, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": sirt_bytes / sirt_s / 1e9 / HBM_PEAK_GBS,
                               "algorithmic_bytes": sirt_bytes}},
@@ -249,7 +264,8 @@ def run_c4(args, P, torch, datagen):
                 "proposals_per_s": steps * cfg["M"] / sat_s if steps else None,
                 "us_per_step": 1e6 * sat_s / steps if steps else None,
                 "accepts": st["accepts"], "resyncs": st["resyncs"], "max_drift_r": st["max_drift_r"],
-                "rmse": rm_sat},
+                "rmse": rm_sat, "rmse_fp64": rm64, "rmse_ratio_fp32_fp64": rm_sat / rm64,
+                "fp64_seconds": sat64_s},
         "data": "synthetic: seeded 30-ellipse phantom, analytic line integrals, Poisson noise I0=1e4",
     }
     copy_probe(args, torch)

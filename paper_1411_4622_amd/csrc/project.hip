@@ -626,61 +626,82 @@ __global__ __launch_bounds__(64) void ray_tile_build_kernel(int N, int U, int K,
     }
 }
 
-// res = Pm - A f per ray, q = res / W (0 where W = 0), and per ray tile the
-// sum of res^2.  One workgroup per ray tile; its 4 wavefronts take a quarter
-// of the tile's steps each, and their sums are added in wavefront order.
+// Forward projection by bands: the steps of all ray tiles are cut into bands
+// of B image rows (or transposed-image rows), B N doubles of each image about
+// a megabyte, and the work items (tile, band) of an XCD run band by band, so
+// that the XCD's L2 holds the image lines its gathers need.  An item writes
+// its 64 partial sums; ray_tile_res_kernel adds them in band order.
+int ray_band(int N)
+{
+    int b = 131072 / (N > 0 ? N : 1);
+    b = b < 8 ? 8 : (b > 256 ? 256 : b);
+    return b & ~7;
+}
+
 template <typename LenT>
-__global__ __launch_bounds__(256) void ray_tile_res_kernel(int N, int U, int K, int nkt, int n_tiles,
-                                                          const double* __restrict__ trig,
-                                                          const uint8_t* __restrict__ off,
-                                                          const LenT* __restrict__ l0,
-                                                          const LenT* __restrict__ l1,
-                                                          const int32_t* __restrict__ base,
-                                                          const int32_t* __restrict__ range,
-                                                          const int64_t* __restrict__ rp,
-                                                          const int32_t* __restrict__ ci,
-                                                          const LenT* __restrict__ ln,
-                                                          const double* __restrict__ f,
-                                                          const double* __restrict__ fT,
-                                                          const double* __restrict__ sino,
-                                                          const double* __restrict__ W,
-                                                          double* __restrict__ out,
-                                                          double* __restrict__ partial)
+__global__ __launch_bounds__(64) void ray_tile_part_kernel(int N, int K, int nkt, int n_tiles, int band,
+                                                           int n_bands, const double* __restrict__ trig,
+                                                           const uint8_t* __restrict__ off,
+                                                           const LenT* __restrict__ l0,
+                                                           const LenT* __restrict__ l1,
+                                                           const int32_t* __restrict__ base,
+                                                           const int32_t* __restrict__ range,
+                                                           const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const LenT* __restrict__ ln,
+                                                           const double* __restrict__ f,
+                                                           const double* __restrict__ fT,
+                                                           double* __restrict__ part)
 {
     constexpr int kS = 8;  // steps in flight
-    __shared__ double part[kWPB][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t t = xcd_tile(n_tiles);
-    if (t < 0) return;
+    const int lane = threadIdx.x;
+    // item j of XCD x (workgroups go to the XCDs round robin): band j / chunk
+    // of tile x chunk + j mod chunk
+    const int64_t chunk = (n_tiles + 7) / 8, j = blockIdx.x / 8;
+    const int64_t bnd = j / chunk, t = (int64_t)(blockIdx.x % 8) * chunk + j % chunk;
+    if (bnd >= n_bands || t >= n_tiles) return;
     const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
     const double* img = ray_cols(trig, u) ? f : fT;
     const int lo = range[2 * t], hi = range[2 * t + 1];
     double acc = 0.0;
     if (hi == kOdd) {
-        if (w == 0 && k < K) {
+        if (bnd == 0 && k < K) {
             const int64_t g = (int64_t)u * K + k;
             for (int64_t q = rp[g]; q < rp[g + 1]; ++q) acc = fma((double)ln[q], f[ci[q]], acc);
         }
-    } else if (lo <= hi) {
-        int a, b;
-        wave_part(lo, hi, w, &a, &b);
+    } else {
+        const int b0 = (int)bnd * band;
+        const int a = lo > b0 ? lo : b0, b = hi < b0 + band - 1 ? hi : b0 + band - 1;
         acc = tile_sum<LenT, kS>(a, b, N, base + t * N, off, l0, l1, t * N * 64 + lane, img);
     }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0) {
-        const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-        double sq = 0.0;
-        if (k < K) {
-            const int64_t g = (int64_t)u * K + k;
-            const double res = sino[g] - sum;
-            const double wg = W[g];
-            out[g] = wg > 0.0 ? res / wg : 0.0;
-            sq = res * res;
-        }
-        sq = wave_sum(sq);
-        if (lane == 0) partial[t] = sq;
+    part[(bnd * n_tiles + t) * 64 + lane] = acc;
+}
+
+// res = Pm - A f per ray (A f the band sums added in band order), q = res / W
+// (0 where W = 0), and per ray tile the sum of res^2.  A wavefront per tile.
+__global__ __launch_bounds__(256) void ray_tile_res_kernel(int K, int nkt, int n_tiles, int n_bands,
+                                                           const double* __restrict__ part,
+                                                           const double* __restrict__ sino,
+                                                           const double* __restrict__ W,
+                                                           double* __restrict__ out,
+                                                           double* __restrict__ partial)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * kWPB + (threadIdx.x >> 6);
+    if (t >= n_tiles) return;
+    const int u = (int)(t / nkt), k = (int)(t - (int64_t)u * nkt) * 64 + lane;
+    double sum = 0.0;
+    for (int b = 0; b < n_bands; ++b) sum += part[((int64_t)b * n_tiles + t) * 64 + lane];
+    double sq = 0.0;
+    if (k < K) {
+        const int64_t g = (int64_t)u * K + k;
+        const double res = sino[g] - sum;
+        const double wg = W[g];
+        out[g] = wg > 0.0 ? res / wg : 0.0;
+        sq = res * res;
     }
+    sq = wave_sum(sq);
+    if (lane == 0) partial[t] = sq;
 }
 
 // 8 x 8 tiles holding at least one support pixel, as (tile row << 16 | tile column)
@@ -704,7 +725,7 @@ std::vector<int32_t> support_tiles(const pila_geom* g)
 // SIRT workspace: factor matrix, scaled residual, block partials, costs,
 // the transposed image and the tile layout
 struct SirtLayout {
-    size_t W, q, partial, sse, fT, tiles, flag, off, l0, l1, base, roff, r0, r1, rbase, range, total;
+    size_t W, q, partial, sse, fT, tiles, flag, off, l0, l1, base, roff, r0, r1, rbase, range, bpart, total;
 };
 
 SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
@@ -738,6 +759,9 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     L.r1 = take(ls * rcells);
     L.rbase = take(sizeof(int32_t) * (rcells / 64));
     L.range = take(sizeof(int32_t) * 2 * nrt);
+    const int band = ray_band(g->n);
+    const size_t n_bands = (size_t)((g->n + band - 1) / band);
+    L.bpart = take(sizeof(double) * n_bands * nrt * 64);
     L.total = at;
     return L;
 }
@@ -860,6 +884,8 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     LenT* r1 = (LenT*)(ws + L.r1);
     int32_t* rbase = (int32_t*)(ws + L.rbase);
     int32_t* range = (int32_t*)(ws + L.range);
+    double* bpart = (double*)(ws + L.bpart);
+    const int band = ray_band(N), n_bands = (N + band - 1) / band;
     ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
                                                      (const LenT*)csr->t_len, roff, r0, r1, rbase, range,
                                                      csr->nnz, aligned16(csr->t_col, csr->t_len), force_csr);
@@ -868,9 +894,11 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     const dim3 tgrid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32));
     for (int32_t it = 0; it < prm->n_iter; ++it) {
         transpose_kernel<<<tgrid, 256, 0, st>>>(N, d_image, fT);
-        ray_tile_res_kernel<LenT><<<xcd_grid(n_rt), 256, 0, st>>>(N, U, K, nkt, n_rt, csr->trig, roff, r0, r1, rbase, range,
-                                                      csr->t_row_ptr, csr->t_col, (const LenT*)csr->t_len,
-                                                      d_image, fT, d_sino, W, q, partial);
+        ray_tile_part_kernel<LenT><<<(unsigned)(8 * ((n_rt + 7) / 8) * n_bands), 64, 0, st>>>(
+            N, K, nkt, n_rt, band, n_bands, csr->trig, roff, r0, r1, rbase, range, csr->t_row_ptr, csr->t_col,
+            (const LenT*)csr->t_len, d_image, fT, bpart);
+        ray_tile_res_kernel<<<(unsigned)((n_rt + kWPB - 1) / kWPB), 256, 0, st>>>(K, nkt, n_rt, n_bands, bpart,
+                                                                                d_sino, W, q, partial);
         reduce_kernel<<<1, 256, 0, st>>>(partial, n_rt, sse + it);
         if (n_tiles > 0)
             tile_back_kernel<LenT><<<xcd_grid(n_tiles), 256, 0, st>>>(

@@ -17,9 +17,11 @@
 //    chain, writes the stats and then done = ticket + 1 with a system-scope
 //    release (which also makes the chain's image writes visible);
 //  * a workgroup that finds no work for idle_us while no chain of its queue
-//    runs (a second device counter counts finished chains) exits; the host
-//    relaunches the kernel on a later call when tickets wait and it has
-//    exited.
+//    runs (a second device counter counts finished chains) closes the queue
+//    by setting the claim counter's top bit, unless a ticket was claimed
+//    meanwhile; then every workgroup of the queue leaves and the kernel
+//    ends.  The host reopens the queue and relaunches the kernel on a later
+//    call when tickets wait and the kernel has ended.
 #include <algorithm>
 #include <chrono>
 #include <cstring>
@@ -60,6 +62,15 @@ static_assert(sizeof(sat_stats) % 8 == 0, "stats are copied in 64-bit words");
 // general body (any row length, M, precision).
 enum { kPiped = 0, kGeneral = 1, kLong = 2 };
 
+// top bit of a queue's claim counter: the queue's kernel is ending
+constexpr unsigned long long kClosed = 1ull << 63;
+
+// before a relaunch: reopen the queue (its previous kernel has ended)
+__global__ void reopen_kernel(unsigned long long* head)
+{
+    if (threadIdx.x == 0) *head &= ~kClosed;
+}
+
 template <int BODY, int CPW, int E>
 __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, RingSlot* slots,
                                                                  uint32_t mask,
@@ -83,6 +94,7 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
                     __hip_atomic_load(&ctl->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 const unsigned long long h =
                     __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (h & kClosed) break;  // the queue was closed: every workgroup leaves
                 if (h < t) {
                     if (atomicCAS(head, h, h + 1) == h) {
                         // acquire once per claim: the slot written before the
@@ -94,11 +106,16 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
                     }
                     continue;
                 }
-                // exit only when idle and no chain of this queue runs: a new
-                // request may follow any running one, and an exited
-                // workgroup does not come back until the kernel ends
+                // idle, and no chain of this queue runs: close the queue (the
+                // claim counter's top bit), so that all its workgroups leave
+                // together and the kernel ends; the compare-and-swap fails if
+                // a ticket was claimed meanwhile.  Workgroups never leave one
+                // by one: the host relaunches only a kernel that has ended,
+                // so a few remaining workgroups would serve every later
+                // request alone.
                 if (++idle > idle_polls &&
-                    __hip_atomic_load(head + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == h)
+                    __hip_atomic_load(head + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == h &&
+                    atomicCAS(head, h, h | kClosed) == h)
                     break;
                 __builtin_amdgcn_s_sleep(127);
             }
@@ -459,6 +476,7 @@ int32_t progress_queue(srv_t* s, Queue& q)
     int lds = s->lds_bytes;
     void* args[] = {&ctl, &slots, &mask, &head, &idle, &lds};
     PILA_TRY(set_lds((const void*)q.shape->k, s->lds_bytes));
+    reopen_kernel<<<1, 64, 0, q.stream>>>(head);
     PILA_HIP(hipLaunchKernel((const void*)q.shape->k, dim3((unsigned)q.groups),
                              dim3((unsigned)(q.shape->waves * kWave)), args, (size_t)s->lds_bytes,
                              q.stream));
