@@ -126,6 +126,8 @@ def main() -> int:
                     help="c5: server slots for the general body")
     ap.add_argument("--long-slots", type=int, default=100,
                     help="c5: server slots for the long-row body (720 angles)")
+    ap.add_argument("--idle-ms", type=float, default=20.0,
+                    help="c5: idle time after which the server's resident kernels end")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

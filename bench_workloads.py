@@ -325,7 +325,7 @@ def run_c5(args, P, torch, datagen):
     log("c5: %d noisy sinograms on the device" % len(noisy))
 
     budget = int(args.mem_budget_gb * (1 << 30))
-    srv = P.Server(mem_budget=budget, idle_us=20000, general_slots=args.general_slots,
+    srv = P.Server(mem_budget=budget, idle_us=int(args.idle_ms * 1000), general_slots=args.general_slots,
                    long_slots=args.long_slots)
     t0 = time.perf_counter()
     for g in geoms.values():
@@ -337,6 +337,7 @@ def run_c5(args, P, torch, datagen):
     torch.cuda.current_stream().synchronize()
     lat, done_at, steps_done, props, rm = [], [], 0, 0, []
     waiting = []  # arrived, not yet admitted
+    by_queue, by_geom = {}, {}  # latencies per server queue and per geometry
     inflight = {}
     nxt = 0
     busy_retries = 0
@@ -362,6 +363,7 @@ def run_c5(args, P, torch, datagen):
                 break
             waiting.pop(0)
             inflight[t] = (a, N, U, ph, img, prm.n_steps)
+            by_queue.setdefault(t & 3, [])
         for t in list(inflight):
             st = srv.poll(t)
             if st is None:
@@ -369,6 +371,8 @@ def run_c5(args, P, torch, datagen):
             a, N, U, ph, img, n_steps = inflight.pop(t)
             fin = time.perf_counter() - start
             lat.append(fin - a)
+            by_queue[t & 3].append(fin - a)
+            by_geom.setdefault("%dx%d" % (N, U), []).append(fin - a)
             done_at.append(fin)
             steps_done += n_steps
             props += n_steps * cfg["M"]
@@ -387,12 +391,18 @@ def run_c5(args, P, torch, datagen):
         "workload": "c5",
         "metric": "slices/s and p50/p99 latency of a Poisson request stream (continuous batching)",
         "requests": n_req, "rate_per_s": args.rate, "sweeps": sweeps, "M": cfg["M"],
+        "server_idle_ms": args.idle_ms,
         "slices_per_s": n_req / span, "proposals_per_s": props / span, "steps_per_s": steps_done / span,
         "latency_ms_p50": float(np.percentile(lat_ms, 50)),
         "latency_ms_p99": float(np.percentile(lat_ms, 99)),
         "latency_ms_mean": float(lat_ms.mean()),
         "span_s": span, "pila_prepare_s": prep_s, "busy_retries": busy_retries,
         "kernel_launches": stat["launches"], "bytes_used_peak_after_prepare": st0["bytes_used"],
+        "latency_s_by_queue": {["pipelined", "general", "long-row"][q]:
+                               {"n": len(v), "p50": float(np.percentile(v, 50)),
+                                "p99": float(np.percentile(v, 99))}
+                               for q, v in sorted(by_queue.items()) if v},
+        "latency_s_p50_by_geometry": {k: float(np.percentile(v, 50)) for k, v in sorted(by_geom.items())},
         "rmse_by_N_sample": {str(N): float(np.mean([r for n, r in rm if n == N]))
                              for N in sorted({n for n, _ in rm})},
         "data": "synthetic: seeded 10-ellipse phantoms (2 per geometry), analytic line integrals, "
