@@ -122,10 +122,12 @@ def main() -> int:
     ap.add_argument("--sweeps", type=float, default=None, help="c3/c5: steps = sweeps x support")
     ap.add_argument("--sat-steps", type=int, default=None, help="c4: chain steps")
     ap.add_argument("--mem-budget-gb", type=float, default=96.0, help="c5: server memory budget")
-    ap.add_argument("--general-slots", type=int, default=4,
+    ap.add_argument("--general-slots", type=int, default=16,
                     help="c5: server slots for the general body")
-    ap.add_argument("--long-slots", type=int, default=100,
+    ap.add_argument("--long-slots", type=int, default=60,
                     help="c5: server slots for the long-row body (720 angles)")
+    ap.add_argument("--max-slots", type=int, default=0,
+                    help="c5: server workgroups in all (0: the library's default)")
     ap.add_argument("--idle-ms", type=float, default=20.0,
                     help="c5: idle time after which the server's resident kernels end")
     args = ap.parse_args()

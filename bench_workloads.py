@@ -325,8 +325,8 @@ def run_c5(args, P, torch, datagen):
     log("c5: %d noisy sinograms on the device" % len(noisy))
 
     budget = int(args.mem_budget_gb * (1 << 30))
-    srv = P.Server(mem_budget=budget, idle_us=int(args.idle_ms * 1000), general_slots=args.general_slots,
-                   long_slots=args.long_slots)
+    srv = P.Server(mem_budget=budget, max_slots=args.max_slots, idle_us=int(args.idle_ms * 1000),
+                   general_slots=args.general_slots, long_slots=args.long_slots)
     t0 = time.perf_counter()
     for g in geoms.values():
         srv.prepare(g)
@@ -391,7 +391,7 @@ def run_c5(args, P, torch, datagen):
         "workload": "c5",
         "metric": "slices/s and p50/p99 latency of a Poisson request stream (continuous batching)",
         "requests": n_req, "rate_per_s": args.rate, "sweeps": sweeps, "M": cfg["M"],
-        "server_idle_ms": args.idle_ms,
+        "server_idle_ms": args.idle_ms, "server_max_slots": args.max_slots,
         "slices_per_s": n_req / span, "proposals_per_s": props / span, "steps_per_s": steps_done / span,
         "latency_ms_p50": float(np.percentile(lat_ms, 50)),
         "latency_ms_p99": float(np.percentile(lat_ms, 99)),

@@ -266,13 +266,15 @@ typedef struct srv_s srv_t; /* opaque server handle */
 typedef struct srv_config {
     size_t mem_budget;       /* device bytes the server allocates at creation and never
                                 exceeds: PILA cache, chain states, build scratch */
-    int32_t max_slots;       /* chains resident at once, one workgroup each, >= 3;
-                                0 = compute units - 8 (the rest stay free for PILA builds) */
+    int32_t max_slots;       /* chains resident at once, one workgroup each (a whole compute
+                                unit), >= 3; 0 = three quarters of the compute units: the
+                                rest stay free for other kernels (the caller's copies, PILA
+                                builds), whose workgroups would otherwise wait for ours */
     int32_t waves_per_chain; /* 4 or 8 (0 = 8) */
     int32_t ring_size;       /* tickets submitted and not yet reaped; power of two, 0 = 1024 */
-    int32_t idle_us;         /* the resident workgroups exit when none of their chains runs
-                                and no request came for this long; the server relaunches
-                                them on the next submission (0 = 20000) */
+    int32_t idle_us;         /* a queue's resident workgroups all exit together when none
+                                of its chains runs and no request came for this long; the
+                                server relaunches them on the next submission (0 = 20000) */
     int32_t general_slots;   /* of max_slots, those that run the general body (chains no
                                 other body takes: FP64, large M); 0 = max_slots / 16 */
     int32_t long_slots;      /* of max_slots, those that run FP32 chains whose rows are too

@@ -577,7 +577,12 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (cfg.mem_budget < ((size_t)1 << 20)) return fail(PILA_ENOMEM, "mem_budget below 1 MiB");
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
-    if (cfg.max_slots == 0) cfg.max_slots = std::max(3, prop.multiProcessorCount - 8);
+    // default: three quarters of the compute units.  A resident workgroup
+    // holds a whole CU (all its LDS and registers), and workgroups of other
+    // kernels (the caller's copies, PILA builds) that the dispatcher sends
+    // to a fully held XCD wait until one of ours leaves; a quarter of each
+    // XCD stays free for them.
+    if (cfg.max_slots == 0) cfg.max_slots = std::max(3, prop.multiProcessorCount * 3 / 4);
     if (cfg.max_slots < 3) return fail(PILA_EINVAL, "max_slots must be at least 3");
     // one resident workgroup per compute unit: all LDS but the static part
     size_t stat = 0;
