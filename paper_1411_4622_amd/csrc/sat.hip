@@ -104,6 +104,7 @@ ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, con
     J.tr_m = nullptr;
     J.tr_acc = nullptr;
     J.tr_dc = nullptr;
+    J.tcol = nullptr;
     J.cancel = nullptr;
     J.cancel_tag = 0;
     return J;
@@ -164,23 +165,31 @@ int32_t set_lds(const void* k, int bytes)
 
 namespace {
 
-// one chain, pipelined body (rows in registers)
-template <typename Real, bool RLDS, int CPW, int E>
+// one chain, pipelined body (rows in registers); TK: slot words from job.tcol
+template <typename Real, bool RLDS, int CPW, int E, bool TK = false>
 __global__ __launch_bounds__(kPipedThreads) void sat_piped_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_piped<Real, RLDS, CPW, E>(job, lds, sh, false);
+    run_chain_piped<Real, RLDS, CPW, E, false, TK>(job, lds, sh, false);
 }
 
 // one segment of a chain whose FP64 resyncs run grid-wide between segments
-template <int CPW, int E>
+template <int CPW, int E, bool TK = false>
 __global__ __launch_bounds__(kPipedThreads) void sat_segment_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_piped<float, false, CPW, E>(job, lds, sh, true);
+    run_chain_piped<float, false, CPW, E, false, TK>(job, lds, sh, true);
+}
+
+// the slot word (ray_slot) of every PILA entry, for the TK kernels
+__global__ __launch_bounds__(256) void tcol_kernel(ChainJob J, int64_t nnz, int32_t* __restrict__ tcol)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += stride)
+        tcol[q] = ray_slot(J, J.col[q]);
 }
 
 // one chain, long-row body (rows of up to 64 E entries, one estimate per wavefront)
@@ -390,14 +399,20 @@ typedef void (*ChainKernel)(ChainJob);
 struct PipedShape {
     int cpw, e;
     ChainKernel k_lds, k_glob, k_seg;
+    ChainKernel k_glob_tk, k_seg_tk;  // FP32: the same with precomputed slot words
 };
 
 template <typename Real, int CPW, int E>
 PipedShape piped_shape()
 {
-    ChainKernel seg = nullptr;
-    if constexpr (sizeof(Real) == 4) seg = sat_segment_kernel<CPW, E>;
-    return {CPW, E, sat_piped_kernel<Real, true, CPW, E>, sat_piped_kernel<Real, false, CPW, E>, seg};
+    ChainKernel seg = nullptr, glob_tk = nullptr, seg_tk = nullptr;
+    if constexpr (sizeof(Real) == 4) {
+        seg = sat_segment_kernel<CPW, E>;
+        glob_tk = sat_piped_kernel<float, false, CPW, E, true>;
+        seg_tk = sat_segment_kernel<CPW, E, true>;
+    }
+    return {CPW, E, sat_piped_kernel<Real, true, CPW, E>, sat_piped_kernel<Real, false, CPW, E>, seg, glob_tk,
+            seg_tk};
 }
 
 const std::vector<PipedShape>& piped_shapes(int precision)
@@ -490,12 +505,27 @@ int32_t launch1(ChainKernel k, ChainJob* J, int threads, int lds, hipStream_t st
 
 using namespace pila;
 
+// Room for the slot words of every PILA entry (one int32 each) that the
+// pipelined FP32 body takes precomputed; offered for geometries of at most
+// 256 angles (rows of at most 2 U <= 512 entries), sized by the bound of two
+// rays per support pixel and angle.
+size_t tcol_bytes(const pila_geom* g, const sat_params* p)
+{
+    if (p->precision != PILA_F32 || g->n_angles > 256) return 0;
+    int64_t sup = (int64_t)g->n * g->n;
+    if (g->mask) {
+        sup = 0;
+        for (int64_t i = 0; i < (int64_t)g->n * g->n; ++i) sup += g->mask[i] != 0;
+    }
+    return align256((size_t)sup * 2 * (size_t)g->n_angles * sizeof(int32_t));
+}
+
 extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes)
 {
     clear_error();
     PILA_TRY(check_geom(geom));
     if (!params || !bytes) return fail(PILA_EINVAL, "params or bytes is NULL");
-    *bytes = chain_bytes(geom, params);
+    *bytes = chain_bytes(geom, params) + tcol_bytes(geom, params);
     return PILA_OK;
 }
 
@@ -533,6 +563,17 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     // rows too long for the pipelined body's registers: the long-row body
     const bool lng = !ps && long_allowed(geom, csr, params);
     const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
+    // the pipelined body in global mode takes the entries' slot words
+    // precomputed when the workspace has room for them
+    const size_t tcb = tcol_bytes(geom, params);
+    const bool tk = ps && !r_in_lds && table_lds <= budget && ps->k_glob_tk && tcb > 0 &&
+                    (size_t)csr->nnz * sizeof(int32_t) <= tcb && ws_bytes >= need + tcb;
+    if (tk) {
+        J.tcol = (const int32_t*)((char*)d_ws + need);
+        if (csr->nnz > 0)
+            tcol_kernel<<<(unsigned)std::min<int64_t>((csr->nnz + 255) / 256, 8192), 256, 0, st>>>(
+                J, csr->nnz, (int32_t*)((char*)d_ws + need));
+    }
     const bool long_seg = lng && !r_in_lds && resync;
     const bool simple_seg = !ps && !lng && !r_in_lds && resync;
     if (piped_seg || long_seg || simple_seg) {
@@ -547,7 +588,7 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         const int sw = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         for (int64_t k = 0; k < n_seg; ++k) {
             if (piped_seg) {
-                PILA_TRY(launch1(ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
+                PILA_TRY(launch1(tk ? ps->k_seg_tk : ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
             } else if (long_seg) {
                 PILA_TRY(launch1(sat_long_segment_kernel<kLongE>, &J, params->m_cand * kWave, long_bytes,
                                  st, &tm));
@@ -562,7 +603,8 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         sat_final_kernel<<<1, 1, 0, st>>>(J);
     } else if (ps && (r_in_lds || table_lds <= budget)) {
         const int lds = r_in_lds ? (int)(G * rs) : table_lds;
-        PILA_TRY(launch1(r_in_lds ? ps->k_lds : ps->k_glob, &J, waves * kWave, lds, st, &tm));
+        PILA_TRY(launch1(r_in_lds ? ps->k_lds : (tk ? ps->k_glob_tk : ps->k_glob), &J, waves * kWave, lds, st,
+                         &tm));
     } else if (lng) {
         const int lds = r_in_lds ? (int)(G * rs) : (int)long_lds(&J, budget);
         ChainKernel k;

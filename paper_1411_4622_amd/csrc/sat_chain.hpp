@@ -76,6 +76,7 @@ struct ChainJob {
     int32_t* tr_m;
     uint8_t* tr_acc;
     double* tr_dc;
+    const int32_t* tcol;     // optional: per PILA entry, the slot word of ray_slot (else NULL)
     const uint64_t* cancel;  // served chains: host word that equals cancel_tag once cancelled
     uint64_t cancel_tag;
 };
@@ -736,6 +737,20 @@ __device__ __forceinline__ void st32(T* base, uint32_t i, T v)
     *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
 }
 
+// Where the residual value of ray g lives in the pipelined body's global
+// mode: the LDS part (angles u < UL, bins k_lo .. k_lo + Kc - 1) as
+// kRaySlotLds | index, else the patch-table slot (2 u + k mod 2) << 13 | k.
+constexpr int kRaySlotLds = (int)0x80000000;
+
+__device__ __forceinline__ int32_t ray_slot(const ChainJob& J, int32_t g)
+{
+    const int u = (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s);  // g / K, g < 2^24
+    const int k = g - u * J.K;
+    const int kk = k - J.k_lo;
+    if (u < J.UL && kk >= 0 && kk < J.Kc) return kRaySlotLds | (u * J.Kc + kk);
+    return ((2 * u + (k & 1)) << 13) | k;
+}
+
 template <typename Real, int E>
 struct RowSet {
     int32_t col[E];
@@ -779,12 +794,16 @@ __device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
     }
 }
 
-template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false>
+// TK: the rows' slot words come precomputed from J.tcol (loaded instead of
+// the ray indices, which are formed back from them where a global residual
+// value is read or written)
+template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false, bool TK = false>
 __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int LPC = kWave / CPW;  // lanes per estimate
     constexpr int BL = kWave / CPW;   // steps per block of draws
-    constexpr int kLdsFlag = (int)0x80000000;
+    constexpr int kLdsFlag = kRaySlotLds;
+    constexpr bool kTK = TK && !RLDS;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
     const int slot = lane / LPC, li = lane % LPC;
     const double KU = (double)J.K * (double)J.U;
@@ -880,24 +899,22 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         for (int e = 0; e < E; ++e) {
             const int q = li + e * LPC;
             const uint32_t at = q < S.n ? b + (uint32_t)q : 0u;
-            S.col[e] = ld32(J.col, at);
+            if (kTK)
+                S.tk[e] = ld32(J.tcol, at);
+            else
+                S.col[e] = ld32(J.col, at);
             S.len[e] = ld32(lenp, at);
         }
     };
     // where each ray of a row lives: LDS index (flagged) or patch-table slot
     auto table_slots = [&](RowSet<Real, E>& S) {
-        if (RLDS) return;
+        if (RLDS || kTK) return;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int g = S.col[e];
-            const int u = (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s);  // g / K, g < 2^24
-            const int k = g - u * J.K;
-            const int kk = k - J.k_lo;
-            if (u < J.UL && kk >= 0 && kk < J.Kc)
-                S.tk[e] = kLdsFlag | (u * J.Kc + kk);
-            else
-                S.tk[e] = ((2 * u + (k & 1)) << 13) | k;
-        }
+        for (int e = 0; e < E; ++e) S.tk[e] = ray_slot(J, S.col[e]);
+    };
+    // ray index of entry e (outside the LDS part)
+    auto gcol = [&](const RowSet<Real, E>& S, int e) -> int32_t {
+        return kTK ? (S.tk[e] >> 14) * J.K + (S.tk[e] & 8191) : S.col[e];
     };
     auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
     // residual value of ray g outside the LDS part
@@ -909,7 +926,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     __syncthreads();  // setup (residual, LDS part, temperatures, patch table) complete
     table_slots(A);
 #pragma unroll
-    for (int e = 0; e < E; ++e) A.rv[e] = in_lds(A.tk[e]) ? rl[A.tk[e] & ~kLdsFlag] : rget(A.col[e]);
+    for (int e = 0; e < E; ++e) A.rv[e] = in_lds(A.tk[e]) ? rl[A.tk[e] & ~kLdsFlag] : rget(gcol(A, e));
     A.fo = J.f[A.p];
     bool patch = false;     // apply the table of step s - 1 to X.rv
     int32_t lp = -1;        // last accepted pixel (step s - 1) and its value
@@ -961,7 +978,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 Y.rv[e] = (Real)0;
-                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = rget(Y.col[e]);
+                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = rget(gcol(Y, e));
             }
         }
         Y.fo = J.f[Y.p];
@@ -983,7 +1000,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                     } else if (X.tk[e] & kLdsFlag) {
                         rl[X.tk[e] & ~kLdsFlag] = rn;
                     } else {
-                        st32(r, (uint32_t)X.col[e], rn);
+                        st32(r, (uint32_t)gcol(X, e), rn);
                         pkey[X.tk[e] >> 13] = ((int64_t)s << 13) | (X.tk[e] & 8191);
                         pval[X.tk[e] >> 13] = rn;
                     }
@@ -1014,7 +1031,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             table_slots(Y);
             __syncthreads();
 #pragma unroll
-            for (int e = 0; e < E; ++e) Y.rv[e] = in_lds(Y.tk[e]) ? rl[Y.tk[e] & ~kLdsFlag] : rget(Y.col[e]);
+            for (int e = 0; e < E; ++e) Y.rv[e] = in_lds(Y.tk[e]) ? rl[Y.tk[e] & ~kLdsFlag] : rget(gcol(Y, e));
             Y.fo = J.f[Y.p];
             lp = -1;
             patch = false;
