@@ -320,8 +320,9 @@ __global__ void sat_final_kernel(ChainJob job)
 // Persistent batch: each workgroup takes chains from a ticket counter until
 // the tickets run out, so every workgroup reaches the exit.  This kernel
 // runs the FP32 chains whose rows and estimates fit the (CPW, E) shape with
-// the pipelined body; sat_batch_simple_kernel runs the others.  Both give the
-// result the chain would give alone.
+// the pipelined body, reading the slot words of their PILA's entries
+// (computed once per PILA and batch); the long-row and general kernels run
+// the others.  All give the result the chain would give alone.
 template <int CPW, int E>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
     const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
         __syncthreads();
         if (j >= n_jobs) break;
         const ChainJob J = jobs[order[j]];
-        run_chain_piped<float, false, CPW, E>(J, lds, sh, false);
+        run_chain_piped<float, false, CPW, E, false, true>(J, lds, sh, false);
     }
 }
 
@@ -637,6 +638,22 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     return PILA_OK;
 }
 
+// The PILAs of a batch whose FP32 chains may take the pipelined body (rows
+// of at most 512 entries): each gets one slot word per entry, shared by the
+// batch's chains on it (their LDS layouts are the same).
+std::vector<const pila_csr*> batch_tcol_pilas(int32_t n_jobs, const sat_job* jobs)
+{
+    std::vector<const pila_csr*> v;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const pila_csr* c = jobs[j].csr;
+        if (!c || jobs[j].params.precision != PILA_F32 || c->max_row > 512 || c->nnz <= 0) continue;
+        bool seen = false;
+        for (const pila_csr* o : v) seen = seen || o->col == c->col;
+        if (!seen) v.push_back(c);
+    }
+    return v;
+}
+
 extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs, size_t* bytes)
 {
     clear_error();
@@ -647,6 +664,7 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
         PILA_TRY(check_geom(jobs[j].geom));
         total += chain_bytes(jobs[j].geom, &jobs[j].params);
     }
+    for (const pila_csr* c : batch_tcol_pilas(n_jobs, jobs)) total += align256(sizeof(int32_t) * (size_t)c->nnz);
     *bytes = total;
     return PILA_OK;
 }
@@ -740,6 +758,23 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     };
     for (std::vector<int>* ids : {&piped_ids, &long_ids, &simple_ids})
         std::stable_sort(ids->begin(), ids->end(), [&](int a, int b) { return work(a) > work(b); });
+    // slot words of the pipelined chains' PILAs (the batch's pipelined kernel reads them)
+    {
+        const std::vector<const pila_csr*> tp = batch_tcol_pilas(n_jobs, jobs);
+        std::vector<int32_t*> where(tp.size(), nullptr);
+        for (int j : piped_ids) {
+            size_t i = 0;
+            while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
+            if (i == tp.size()) return fail(PILA_EINVAL, "job %d: no slot-word room for its PILA", j);
+            if (!where[i]) {
+                where[i] = (int32_t*)cur;
+                cur += align256(sizeof(int32_t) * (size_t)tp[i]->nnz);
+                tcol_kernel<<<(unsigned)std::min<int64_t>((tp[i]->nnz + 255) / 256, 8192), 256, 0, st>>>(
+                    host[j], tp[i]->nnz, where[i]);
+            }
+            host[j].tcol = where[i];
+        }
+    }
     std::vector<int> order(piped_ids);
     order.insert(order.end(), long_ids.begin(), long_ids.end());
     order.insert(order.end(), simple_ids.begin(), simple_ids.end());
