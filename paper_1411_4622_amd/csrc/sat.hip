@@ -521,6 +521,13 @@ size_t tcol_bytes(const pila_geom* g, const sat_params* p)
     return align256((size_t)sup * 2 * (size_t)g->n_angles * sizeof(int32_t));
 }
 
+int32_t pila::launch_tcol(const ChainJob& J, int64_t nnz, int32_t* dst, hipStream_t st)
+{
+    if (nnz > 0) tcol_kernel<<<(unsigned)std::min<int64_t>((nnz + 255) / 256, 8192), 256, 0, st>>>(J, nnz, dst);
+    PILA_HIP(hipGetLastError());
+    return PILA_OK;
+}
+
 extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes)
 {
     clear_error();

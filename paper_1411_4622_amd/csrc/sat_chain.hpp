@@ -120,6 +120,10 @@ __device__ __forceinline__ T lane0(T x)
     return x;
 }
 
+// uniform_job below copies every field by name: a field added to ChainJob
+// must be added there too (this size check is the reminder)
+static_assert(sizeof(ChainJob) == 312, "ChainJob changed: update uniform_job");
+
 __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
 {
     ChainJob J;
@@ -130,7 +134,7 @@ __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
     PILA_F(T0) PILA_F(TN) PILA_F(tn_ratio) PILA_F(delta_max) PILA_F(f_min) PILA_F(f_max) PILA_F(ln09)
     PILA_F(row_ptr) PILA_F(col) PILA_F(len) PILA_F(t_row_ptr) PILA_F(t_col) PILA_F(t_len)
     PILA_F(support) PILA_F(sino) PILA_F(f) PILA_F(r) PILA_F(tsum) PILA_F(tdrift) PILA_F(carry)
-    PILA_F(stats) PILA_F(tr_m) PILA_F(tr_acc) PILA_F(tr_dc) PILA_F(cancel) PILA_F(cancel_tag)
+    PILA_F(stats) PILA_F(tr_m) PILA_F(tr_acc) PILA_F(tr_dc) PILA_F(tcol) PILA_F(cancel) PILA_F(cancel_tag)
 #undef PILA_F
     return J;
 }

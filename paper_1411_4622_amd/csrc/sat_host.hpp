@@ -28,6 +28,9 @@ bool long_allowed(const pila_geom* g, const pila_csr* c, const sat_params* p);
 // LDS bytes of a long-row chain with the residual partly in LDS; sets J->UL
 int64_t long_lds(ChainJob* J, int64_t budget);
 int32_t set_lds(const void* k, int bytes);
+// the slot words of a PILA's nnz entries for the pipelined body in global
+// mode, for J's LDS layout (J.UL set), written to dst on stream st
+int32_t launch_tcol(const ChainJob& J, int64_t nnz, int32_t* dst, hipStream_t st);
 
 // pila_build with a caller-supplied device scratch of pila_build_scratch(geom) bytes
 size_t pila_build_scratch(const pila_geom* geom);

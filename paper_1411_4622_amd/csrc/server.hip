@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
         const bool cancelled = __builtin_amdgcn_readfirstlane(flags_s[0]) != 0;
         if (!cancelled) {
             if constexpr (BODY == kPiped)
-                run_chain_piped<float, false, CPW, E, true>(J, lds, sh, false);
+                run_chain_piped<float, false, CPW, E, true, true>(J, lds, sh, false);
             else if constexpr (BODY == kLong)
                 run_chain_long<float, false, E, true>(J, lds, sh, false);
             else if (J.precision == PILA_F32)
@@ -266,6 +266,7 @@ struct PilaEntry {
     pila_geom geom;
     pila_csr csr;
     std::vector<Block> blocks;
+    int32_t* tcol = nullptr;  // slot words of the entries (pipelined FP32 chains), or NULL
     int refs = 0;
     uint64_t last_use = 0;
 };
@@ -445,6 +446,20 @@ int32_t cache_get(srv_t* s, const pila_geom* g, PilaEntry** out)
                       (void**)&e->csr.support};
     PILA_TRY(take(sizes2, dst2, 5));
     PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, s->build_stream));
+    // FP32 rows the pipelined body can hold: the slot words of the entries
+    // for the server's LDS layout (the same for every chain on this PILA)
+    if (g->len_dtype == PILA_F32 && e->csr.max_row <= 512 && piped_allowed(&e->geom, &e->csr)) {
+        const size_t sizes3[1] = {sizeof(int32_t) * nnz};
+        void** dst3[1] = {(void**)&e->tcol};
+        PILA_TRY(take(sizes3, dst3, 1));
+        sat_params prm{};
+        prm.precision = PILA_F32;
+        prm.m_cand = 1;
+        prm.n_stages = 1;
+        ChainJob J = make_job(&e->geom, &e->csr, nullptr, &prm, nullptr, nullptr);
+        hybrid_lds(&J, s->lds_bytes);
+        PILA_TRY(launch_tcol(J, e->csr.nnz, e->tcol, s->build_stream));
+    }
     e->last_use = ++s->use_clock;
     *out = e.get();
     guard.e = nullptr;
@@ -657,7 +672,7 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     ChainJob probe = make_job(&e->geom, &e->csr, req->d_sino, &req->params, req->d_image, nullptr);
     const bool f32 = req->params.precision == PILA_F32;
     int qi = kGeneral;
-    if (f32 && piped_allowed(&e->geom, &e->csr) && req->params.m_cand <= ps->waves * ps->cpw &&
+    if (f32 && e->tcol && piped_allowed(&e->geom, &e->csr) && req->params.m_cand <= ps->waves * ps->cpw &&
         e->csr.max_row <= (kWave / ps->cpw) * ps->e && hybrid_lds(&probe, s->lds_bytes) <= s->lds_bytes)
         qi = kPiped;
     else if (f32 && long_allowed(&e->geom, &e->csr, &req->params) &&
@@ -675,7 +690,10 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     Block ws;
     if (!alloc_evicting(s, cb, e, &ws)) return fail(PILA_EBUSY, "no room for the chain state now");
     ChainJob J = make_job(&e->geom, &e->csr, req->d_sino, &req->params, req->d_image, s->arena.at(ws.off));
-    if (qi == kPiped) hybrid_lds(&J, s->lds_bytes);
+    if (qi == kPiped) {
+        hybrid_lds(&J, s->lds_bytes);
+        J.tcol = e->tcol;
+    }
     if (qi == kLong) long_lds(&J, s->lds_bytes);
     RingSlot& sl = q.slots[l & s->mask];
     J.cancel = &q.d_slots[l & s->mask].cancel;
