@@ -278,7 +278,7 @@ typedef struct srv_config {
     int32_t general_slots;   /* of max_slots, those that run the general body (chains no
                                 other body takes: FP64, large M); 0 = max_slots / 16 */
     int32_t long_slots;      /* of max_slots, those that run FP32 chains whose rows are too
-                                long for the pipelined body's registers (up to 1024
+                                long for the pipelined body's registers (up to 1536
                                 entries); 0 = max_slots / 4.  The rest run the pipelined
                                 body */
 } srv_config;

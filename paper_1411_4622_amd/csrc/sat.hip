@@ -146,7 +146,8 @@ int64_t hybrid_lds(ChainJob* J, int64_t budget)
 
 bool long_allowed(const pila_geom* g, const pila_csr* c, const sat_params* p)
 {
-    return piped_allowed(g, c) && c->max_row <= kWave * kLongE && p->m_cand <= kPipedThreads / kWave;
+    return piped_allowed(g, c) && c->max_row <= kWave * (kLongE + kLongOver) &&
+           p->m_cand <= kPipedThreads / kWave;
 }
 
 int64_t long_lds(ChainJob* J, int64_t budget)
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void tcol_kernel(ChainJob J, int64_t nnz, int3
         tcol[q] = ray_slot(J, J.col[q]);
 }
 
-// one chain, long-row body (rows of up to 64 E entries, one estimate per wavefront)
+// one chain, long-row body (64 E entries per row in registers, one estimate per wavefront)
 template <typename Real, bool RLDS, int E>
 __global__ __launch_bounds__(kPipedThreads) void sat_long_kernel(ChainJob job)
 {

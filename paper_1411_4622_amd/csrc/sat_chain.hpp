@@ -1095,9 +1095,11 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 }
 
 // ---------------------------------------------------------------------------
-// long rows: one estimate per wavefront, rows of up to 64 E entries in
-// registers one step ahead; residual values are read at the start of each
-// step (after the previous step's scatter), so no patch table is needed.
+// long rows: one estimate per wavefront, the first 64 E entries of a row in
+// registers one step ahead (any further entries, as in the central pixels of
+// an even bin count at 720 angles, are read in place during the step);
+// residual values are read at the start of each step (after the previous
+// step's scatter), so no patch table is needed.
 // The residual lives in LDS for angles u < UL (over bins k_lo .. k_lo+Kc-1,
 // at the start of the dynamic LDS) and in global memory otherwise, or wholly
 // in LDS (RLDS).  Same canonical sums and decision as the other bodies.
@@ -1107,6 +1109,7 @@ struct LongRow {
     int32_t col[E];
     Real len[E];
     int32_t p, n;
+    uint32_t b;  // first entry of the row
     double delta, N1, lnN1;
 };
 
@@ -1159,6 +1162,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
         if (t >= n_steps) {
             S.p = 0;
             S.n = 0;
+            S.b = 0;
             S.delta = S.N1 = S.lnN1 = 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -1179,6 +1183,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
         S.p = __shfl(cur.p, j, kWave);
         S.n = __shfl(cur.n, j, kWave);
         const uint32_t b = (uint32_t)__shfl((int)cur.b, j, kWave);
+        S.b = b;
         S.delta = __shfl(cur.delta, j, kWave);
         S.N1 = __shfl(cur.N1, j, kWave);
         S.lnN1 = __shfl(cur.lnN1, j, kWave);
@@ -1231,6 +1236,13 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
             const Real t = (lane + e * kWave < X.n) ? dr * X.len[e] : (Real)0;
             part[0] = fma(t, (Real)2 * rv[e] + t, part[0]);
         }
+        // entries beyond the registers (rows longer than 64 E), read in
+        // place, in the same per-lane order
+        for (int q = kWave * E + lane; q < X.n; q += kWave) {
+            int lo;
+            const Real t = dr * ld32(lenp, X.b + (uint32_t)q);
+            part[0] = fma(t, (Real)2 * rget(ld32(J.col, X.b + (uint32_t)q), &lo) + t, part[0]);
+        }
         const Real S = canon_sum<kWave>(part);
         if (active && lane == 0) {
             sh.S[wave] = (double)S;
@@ -1254,6 +1266,19 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
                     else
                         st32(r, (uint32_t)X.col[e], rn);
                 }
+            }
+            // the entries beyond the registers: their rays differ from the
+            // row's others, so their values are still the ones summed
+            for (int q = kWave * E + lane; q < X.n; q += kWave) {
+                const int32_t g = ld32(J.col, X.b + (uint32_t)q);
+                int lo;
+                const Real rn = rget(g, &lo) + dr * ld32(lenp, X.b + (uint32_t)q);
+                if (RLDS)
+                    r[g] = rn;
+                else if (lo >= 0)
+                    rl[lo] = rn;
+                else
+                    st32(r, (uint32_t)g, rn);
             }
             if (lane == 0) J.f[X.p] = fn;
         }

@@ -21,8 +21,10 @@ int device_props(hipDeviceProp_t* prop);
 bool piped_allowed(const pila_geom* g, const pila_csr* c);
 // LDS bytes of a pipelined chain with the residual partly in LDS; sets J->UL
 int64_t hybrid_lds(ChainJob* J, int64_t budget);
-// rows per lane in registers of the long-row body (rows up to 64 kLongE entries)
+// row entries per lane in registers of the long-row body (64 kLongE per
+// row); up to kLongOver more per lane are read in place
 constexpr int kLongE = 16;
+constexpr int kLongOver = 8;
 // whether the long-row body takes this chain (one estimate per wavefront)
 bool long_allowed(const pila_geom* g, const pila_csr* c, const sat_params* p);
 // LDS bytes of a long-row chain with the residual partly in LDS; sets J->UL

@@ -223,10 +223,16 @@ def test_segmented_general_body_matches_in_group(P):
     assert st[0]["accepts"] == st_seg["accepts"] and st[0]["resyncs"] == st_seg["resyncs"]
 
 
-def test_long_rows_fp64_match_oracle(P):
+@pytest.mark.parametrize("U,K", [(420, 23), (720, 22)])
+def test_long_rows_fp64_match_oracle(P, U, K):
     """420 angles: rows of more than 512 entries, which the long-row body
-    (one estimate per wavefront, rows in registers) takes."""
-    sl = _slice(16, 420, 23, seed=71, masked=True, I0=1e4)
+    (one estimate per wavefront, rows in registers) takes; 720 angles with an
+    even bin count: the central pixels' rows (1050 entries) go past the
+    registers' 1024 and their last entries are read in place."""
+    sl = _slice(16, U, K, seed=71, masked=True, I0=1e4)
+    if U == 720:
+        geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f64")
+        assert P.pila_build(geom).max_row > 1024
     prm = P.SatParams(n_steps=4000, seed=19, chain_id=3, m_cand=6, T0=None, q_auto=30,
                       n_stages=40, delta_max=0.05)
     g = _gpu_chain(P, sl, "f64", prm)
@@ -234,19 +240,21 @@ def test_long_rows_fp64_match_oracle(P):
     _compare_fp64(g, _oracle_chain(sl, prm))
 
 
-def test_long_rows_fp32_alone_batched_served_agree(P):
+@pytest.mark.parametrize("U,K", [(420, 114), (720, 114)])
+def test_long_rows_fp32_alone_batched_served_agree(P, U, K):
     """FP32 long rows with the residual partly in LDS: alone (segments with
     grid-wide resyncs), in a batch and served (in-workgroup resyncs) give the
-    same bits."""
-    sl = _slice(80, 420, 114, seed=73, masked=True, I0=1e4)
-    assert 420 * 114 * 4 > 160 * 1024
+    same bits; at 720 angles and an even bin count some rows are longer than
+    the registers hold."""
+    sl = _slice(80, U, K, seed=73, masked=True, I0=1e4)
+    assert U * K * 4 > 160 * 1024
     prm = P.SatParams(n_steps=6000, seed=23, chain_id=1, m_cand=8, T0=None, q_auto=30,
                       precision="f32", resync_every=300, n_stages=30)
     f_alone, st_alone, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
     assert st_alone["resyncs"] >= 2 and st_alone["chain_launches"] > 1
     geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
     pl = P.pila_build(geom)
-    assert pl.max_row > 512
+    assert pl.max_row > (1024 if U == 720 else 512)
     sino = torch.from_numpy(sl.sino).cuda()
     img = torch.from_numpy(sl.f0.copy()).cuda()
     st = P.sat_run_batch([P.Job(pl, sino, img, prm)], waves_per_chain=8, chains_per_cu=1)
