@@ -695,9 +695,23 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
             const Real* len = (const Real*)J.len;
             const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
             const Real dr = (Real)d_star;
-            for (int64_t q = b + lane; q < e; q += kWave) {
-                const int32_t g = J.col[q];
-                r[g] = r[g] + dr * len[q];
+            // U entries per lane loaded before any is written (the row's rays
+            // are distinct, so no write changes a value read here)
+            constexpr int U = 4;
+            for (int64_t q0 = b + lane; q0 < e; q0 += (int64_t)kWave * U) {
+                int32_t cc[U];
+                Real ll[U], rr[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    const int64_t q = q0 + (int64_t)c * kWave < e ? q0 + (int64_t)c * kWave : b;
+                    cc[c] = J.col[q];
+                    ll[c] = len[q];
+                }
+#pragma unroll
+                for (int c = 0; c < U; ++c) rr[c] = r[cc[c]];
+#pragma unroll
+                for (int c = 0; c < U; ++c)
+                    if (q0 + (int64_t)c * kWave < e) r[cc[c]] = rr[c] + dr * ll[c];
             }
             if (lane == 0) J.f[p] = sh.fn[dn.ms];
         }
