@@ -239,7 +239,11 @@ typedef struct sirt_params {
     double lambda; /* relaxation; 1 is the unrelaxed update */
 } sirt_params;
 
-/* sirt_workspace_size - device workspace bytes that sirt_run needs. */
+/* sirt_workspace_size - device workspace bytes that sirt_run needs: the
+ * factor matrix, residuals and partial sums, the transposed image and the two
+ * tile layouts sirt_run builds from the PILA (about 9 bytes per (pixel,
+ * angle) of the support's 8 x 8 tiles and 9 bytes per (ray, image row or
+ * column) in FP32; 15 GB at 1024 x 1024 and 720 angles). */
 int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params* params, size_t* bytes);
 
 /*
@@ -249,7 +253,12 @@ int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params* params, si
  * by (lambda / U) * sum over its row of l * res_g / W_g (Eq. 10-11 summed
  * over all rays crossing the pixel).  d_image (N*N) in: start, out: result.
  * h_cost (nullable, n_iter doubles) receives Eq. 4 of the image entering
- * each iteration; the call then synchronises.
+ * each iteration; the call then synchronises.  Both projections run on
+ * tile layouts built at the start of the call; a tile whose entries do not
+ * have the two-neighbour shape is summed from the CSR rows instead (the
+ * environment variable PILA_SIRT_CSR=1 forces that for every tile, for
+ * tests).  Sums are deterministic; their order differs from a row walk, so
+ * results match the plain definition to rounding (1e-10 relative in tests).
  */
 int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
                  const sirt_params* params, double* d_image, void* d_ws, size_t ws_bytes,
