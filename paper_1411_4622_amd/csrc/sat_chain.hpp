@@ -272,12 +272,15 @@ __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_read
 struct Schedule {
     int64_t stage, next;  // current stage, first step of the following stage
     double T0, dT;
+    double T, invT;  // temperature of the current stage and its reciprocal
     __device__ void start(int64_t s, int64_t n_steps, int32_t n_stages, double t0, double tn)
     {
         T0 = t0;
         dT = (t0 - tn) / (double)n_stages;
         stage = n_steps > 0 ? (s * (int64_t)n_stages) / n_steps : 0;
         next = first_of(stage + 1, n_steps, n_stages);
+        T = T0 - (double)stage * dT;
+        invT = 1.0 / T;
     }
     __device__ static int64_t first_of(int64_t k, int64_t n_steps, int32_t n_stages)
     {
@@ -285,11 +288,15 @@ struct Schedule {
     }
     __device__ double at(int64_t s, int64_t n_steps, int32_t n_stages)
     {
-        while (s >= next) {
-            ++stage;
-            next = first_of(stage + 1, n_steps, n_stages);
+        if (s >= next) {
+            while (s >= next) {
+                ++stage;
+                next = first_of(stage + 1, n_steps, n_stages);
+            }
+            T = T0 - (double)stage * dT;
+            invT = 1.0 / T;
         }
-        return T0 - (double)stage * dT;
+        return T;
     }
 };
 
@@ -956,10 +963,11 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     // Returns true when the chain stops here: a segmented chain for a
     // resync, or a served chain that has been cancelled (then cancelled is set).
     bool cancelled = false;
+    double co = sqrt(cs.sse / KU);  // C of Eq. 4 before the step
     auto step = [&](RowSet<Real, E>& X, RowSet<Real, E>& Y, RowSet<Real, E>& Z, int64_t s)
                     __attribute__((always_inline)) -> bool {
         const double T = sched.at(s, n_steps, J.n_stages);
-        const double invT = 1.0 / T;
+        const double invT = sched.invT;
         if (!RLDS && patch) {  // the previous step's accepted change
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -1001,7 +1009,6 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         }
         Y.fo = J.f[Y.p];
         prefetch(Z, s + 2);
-        const double co = sqrt(cs.sse / KU);
         if (SERVED) cancel_probe(J, sh, s);
         __syncthreads();
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, X.N1, X.lnN1);
@@ -1031,6 +1038,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             }
         }
         count_decision(J, cs, dn, d_star, s);
+        if (dn.accept && dn.S != 0.0) co = sqrt(cs.sse / KU);  // C of Eq. 4 only moves with the SSE
         if (sizeof(Real) == 4 && J.resync_every > 0 && cs.since >= J.resync_every) {
             if (!RLDS) {
                 __syncthreads();
@@ -1041,6 +1049,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 return true;
             }
             resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            co = sqrt(cs.sse / KU);
             if (!RLDS) lds_residual_load<Real>(J, r, rl);
             // the next two sets are drawn again after the rebuild, so that no
             // row stays in registers across it
