@@ -268,3 +268,26 @@ def test_long_rows_fp32_alone_batched_served_agree(P, U, K):
         while srv.poll(t) is None:
             pass
     assert np.array_equal(img2.cpu().numpy(), f_alone)
+
+
+@pytest.mark.parametrize("U,K,steps", [(300, 151, 5000), (240, 201, 5000)])
+def test_slot_words_match_computed_slots(P, U, K, steps):
+    """The pipelined body that loads precomputed slot words (batches always;
+    sat_run up to 256 angles) gives the bits of the one that forms them per
+    entry (sat_run above 256 angles), and the FP32 chain stays within the
+    drift bound of its FP64 resyncs."""
+    sl = _slice(64, U, K, seed=81, masked=True, I0=1e4)
+    assert U * K * 4 > 160 * 1024  # residual partly in global memory
+    prm = P.SatParams(n_steps=steps, seed=29, chain_id=2, m_cand=8, T0=None, q_auto=30,
+                      precision="f32", resync_every=400, n_stages=30)
+    f_alone, st_alone, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
+    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    pl = P.pila_build(geom)
+    assert pl.max_row <= 512  # the pipelined body
+    sino = torch.from_numpy(sl.sino).cuda()
+    img = torch.from_numpy(sl.f0.copy()).cuda()
+    st = P.sat_run_batch([P.Job(pl, sino, img, prm)], waves_per_chain=8, chains_per_cu=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(img.cpu().numpy(), f_alone)
+    assert st[0]["accepts"] == st_alone["accepts"] and st[0]["resyncs"] == st_alone["resyncs"] >= 2
+    assert st_alone["max_drift_r"] < 1e-3
