@@ -5,8 +5,8 @@ baseline leg of the benchmark may import this package; the product path
 (paper_1411_4622_amd) never does, and this package never imports it.
 
 Each function states the passage of the paper it follows; the C source
-holds the arithmetic.  Parity of the FP32-residual chain mode is an
-approximation by design and has no exact pin (only drift bounds).
+holds the arithmetic.  The FP32-residual chain mode is an approximation by
+design; it is pinned by rounding-error bounds (see oracle.c).
 """
 from __future__ import annotations
 
@@ -38,7 +38,12 @@ class SatParams(C.Structure):
                 ("n_stages", C.c_int32), ("m_cand", C.c_int32), ("T0", C.c_double),
                 ("TN", C.c_double), ("q_auto", C.c_int32), ("precision", C.c_int32),
                 ("tn_ratio", C.c_double), ("delta_max", C.c_double), ("f_min", C.c_double),
-                ("f_max", C.c_double), ("resync_every", C.c_int64)]
+                ("f_max", C.c_double), ("resync_every", C.c_int64), ("schedule", C.c_int32),
+                ("proposal", C.c_int32)]
+
+
+SCHEDULES = {"linear": 0, "exp": 1, "cubic": 2}
+PROPOSALS = {"clamp": 0, "redraw": 1}
 
 
 class SatStats(C.Structure):
@@ -66,10 +71,25 @@ def _load():
     lib.or_pixel_row.restype = C.c_int32
     lib.or_forward.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P]
     lib.or_backward.argtypes = [C.c_int32, P, P, P, P, P]
-    lib.or_temperature.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double]
+    lib.or_temperature.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_double, C.c_double,
+                                   C.c_int32]
     lib.or_temperature.restype = C.c_double
-    lib.or_sat_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.or_sat_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.or_sat_run.restype = C.c_int
+    lib.or_delta_sse64.argtypes = [P, P, P, P, C.c_int32, C.c_double, P]
+    lib.or_delta_sse64.restype = C.c_double
+    lib.or_delta_sse32.argtypes = [P, P, P, P, C.c_int32, C.c_double]
+    lib.or_delta_sse32.restype = C.c_float
+    lib.or_sirt_seq_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int64, P,
+                                    C.c_int32, C.c_int64, C.c_double, C.c_uint64, P, P]
+    lib.or_sirt_seq_run.restype = C.c_int
+    lib.or_drt_half_span.argtypes = [C.c_int32]
+    lib.or_drt_half_span.restype = C.c_int32
+    lib.or_drt.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P]
+    lib.or_satdrt_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P, P, P]
+    lib.or_satdrt_run.restype = C.c_int
+    lib.or_quantize_u8.argtypes = [C.c_int64, P, P]
+    lib.or_dequantize_u8.argtypes = [C.c_int64, P, P]
     lib.or_sirt_run.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32,
                                 C.c_double, P, P]
     lib.or_sirt_run.restype = C.c_int
@@ -162,9 +182,11 @@ def backward(N: int, csr, y) -> np.ndarray:
     return out.reshape(N, N)
 
 
-def temperature(s: int, n_steps: int, n_stages: int, T0: float, TN: float) -> float:
-    """Eq. 2 evaluated at the stage of step s."""
-    return float(_load().or_temperature(s, n_steps, n_stages, T0, TN))
+def temperature(s: int, n_steps: int, n_stages: int, T0: float, TN: float,
+                schedule: str = "linear") -> float:
+    """Temperature at the stage of step s: Eq. 2 (linear), the exponential
+    schedule of section III-C (its second Eq. 8) or the cubic one (Eq. 9)."""
+    return float(_load().or_temperature(s, n_steps, n_stages, T0, TN, SCHEDULES[schedule]))
 
 
 def make_params(**kw) -> SatParams:
@@ -183,11 +205,15 @@ def make_params(**kw) -> SatParams:
     p.f_min = kw.get("f_min", 0.0)
     p.f_max = kw.get("f_max", 1.0)
     p.resync_every = kw.get("resync_every", 0)
+    p.schedule = SCHEDULES[kw.get("schedule", "linear")]
+    p.proposal = PROPOSALS[kw.get("proposal", "clamp")]
     return p
 
 
-def sat_run(N: int, U: int, K: int, csr, sino, f0, mask=None, trace: bool = True, **kw):
-    """One SAT chain (section II-A/B, BoME of III-B).  Returns (f, stats, trace)."""
+def sat_run(N: int, U: int, K: int, csr, sino, f0, mask=None, trace: bool = True,
+            residual: bool = False, **kw):
+    """One SAT chain (section II-A/B, BoME of III-B).  Returns (f, stats, trace),
+    and the final running residual (U x K) as a fourth item when residual=True."""
     row_ptr, col, ln = csr
     prm = make_params(**kw)
     f = np.ascontiguousarray(f0, dtype=np.float64).reshape(-1).copy()
@@ -199,13 +225,16 @@ def sat_run(N: int, U: int, K: int, csr, sino, f0, mask=None, trace: bool = True
     if trace:
         tr = dict(m_star=np.zeros(n, np.int32), accept=np.zeros(n, np.uint8),
                   dC=np.zeros(n, np.float64), scale=np.zeros(n, np.float64))
+    r_out = np.zeros(U * K, dtype=np.float64) if residual else None
     rc = _load().or_sat_run(N, U, K, _p(m), _p(row_ptr), _p(col), _p(ln), _p(s), C.byref(prm),
                             _p(f), C.byref(st), _p(tr["m_star"]) if tr else None,
                             _p(tr["accept"]) if tr else None, _p(tr["dC"]) if tr else None,
-                            _p(tr["scale"]) if tr else None)
+                            _p(tr["scale"]) if tr else None, _p(r_out))
     if rc != 0:
         raise RuntimeError("oracle sat_run failed with %d" % rc)
     stats = {k: getattr(st, k) for k, _ in SatStats._fields_ if k != "pad"}
+    if residual:
+        return f.reshape(N, N), stats, tr, r_out.reshape(U, K)
     return f.reshape(N, N), stats, tr
 
 
@@ -217,3 +246,91 @@ def sirt_run(N: int, U: int, K: int, csr, sino, f0, n_iter: int, lam: float):
     cost = np.zeros(n_iter, dtype=np.float64)
     _load().or_sirt_run(N, U, K, _p(row_ptr), _p(col), _p(ln), _p(s), n_iter, lam, _p(f), _p(cost))
     return f.reshape(N, N), cost
+
+
+def delta_sse(csr, r, p: int, d: float, fp32: bool = False):
+    """Eq. 7's inner sum for pixel p changed by d against residual r: FP64
+    (returns (S, sum of |terms|)) or with the FP32 operands and accumulation
+    of an FP32 chain (returns S as a float)."""
+    row_ptr, col, ln = csr
+    lib = _load()
+    if fp32:
+        r32 = np.ascontiguousarray(r, dtype=np.float32).reshape(-1)
+        return float(lib.or_delta_sse32(_p(row_ptr), _p(col), _p(ln), _p(r32), int(p), float(d)))
+    r64 = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+    a = C.c_double(0.0)
+    S = lib.or_delta_sse64(_p(row_ptr), _p(col), _p(ln), _p(r64), int(p), float(d), C.byref(a))
+    return float(S), float(a.value)
+
+
+def support_of(N: int, mask=None) -> np.ndarray:
+    m = np.ones(N * N, np.uint8) if mask is None else np.asarray(mask, np.uint8).reshape(-1)
+    return np.flatnonzero(m).astype(np.int32)
+
+
+def sirt_seq_run(N: int, U: int, K: int, csr, sino, f0, n_iter: int, m_per: int, lam: float,
+                 seed: int, mask=None):
+    """SIRT pixel by pixel (section III-D as described, Eq. 10-11): n_iter
+    iterations of m_per pixel updates, pixels drawn at random over the
+    support.  Returns (f, cost after each iteration)."""
+    row_ptr, col, ln = csr
+    sup = support_of(N, mask)
+    f = np.ascontiguousarray(f0, dtype=np.float64).reshape(-1).copy()
+    s = np.ascontiguousarray(sino, dtype=np.float64).reshape(-1)
+    cost = np.zeros(max(n_iter, 1), dtype=np.float64)
+    rc = _load().or_sirt_seq_run(N, U, K, _p(row_ptr), _p(col), _p(ln), _p(s), len(sup), _p(sup),
+                                 int(n_iter), int(m_per), float(lam), int(seed), _p(f), _p(cost))
+    if rc != 0:
+        raise RuntimeError("oracle sirt_seq_run failed with %d" % rc)
+    return f.reshape(N, N), cost[:n_iter]
+
+
+def drt_half_span(N: int) -> int:
+    """Samples of the bilinear DRT run at t = -T .. T along each ray."""
+    return int(_load().or_drt_half_span(N))
+
+
+def drt(N: int, U: int, K: int, angles, f) -> np.ndarray:
+    """Eq. 1 the conventional way (section III-A's comparison): U x K
+    sinogram of image f by bilinear interpolation at unit steps."""
+    a = np.ascontiguousarray(angles, dtype=np.float64)
+    fv = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    out = np.zeros(U * K, dtype=np.float64)
+    _load().or_drt(N, U, K, _p(a), _p(fv), _p(out))
+    return out.reshape(U, K)
+
+
+def satdrt_run(N: int, U: int, K: int, angles, sino, f0, mask=None, **kw):
+    """SAT whose evaluation step projects each estimate's whole image with the
+    bilinear DRT (section III-A's comparison method).  T0/TN must be given.
+    Returns (f, final cost, trace)."""
+    prm = make_params(**kw)
+    a = np.ascontiguousarray(angles, dtype=np.float64)
+    f = np.ascontiguousarray(f0, dtype=np.float64).reshape(-1).copy()
+    s = np.ascontiguousarray(sino, dtype=np.float64).reshape(-1)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+    n = prm.n_steps
+    tr = dict(m_star=np.zeros(max(n, 1), np.int32), accept=np.zeros(max(n, 1), np.uint8),
+              dC=np.zeros(max(n, 1), np.float64))
+    cf = C.c_double(0.0)
+    rc = _load().or_satdrt_run(N, U, K, _p(a), _p(m), _p(s), C.byref(prm), _p(f),
+                               _p(tr["m_star"]), _p(tr["accept"]), _p(tr["dC"]), C.byref(cf))
+    if rc != 0:
+        raise RuntimeError("oracle satdrt_run failed with %d" % rc)
+    return f.reshape(N, N), float(cf.value), {k: v[:n] for k, v in tr.items()}
+
+
+def quantize_u8(lengths) -> np.ndarray:
+    """One-byte lengths of section II-B: round(180 l)."""
+    ln = np.ascontiguousarray(lengths, dtype=np.float64).reshape(-1)
+    q = np.zeros(len(ln), dtype=np.uint8)
+    _load().or_quantize_u8(len(ln), _p(ln), _p(q))
+    return q
+
+
+def dequantize_u8(q) -> np.ndarray:
+    """The length each byte stands for, q / 180 in float, widened to double."""
+    qq = np.ascontiguousarray(q, dtype=np.uint8).reshape(-1)
+    out = np.zeros(len(qq), dtype=np.float64)
+    _load().or_dequantize_u8(len(qq), _p(qq), _p(out))
+    return out

@@ -20,10 +20,16 @@
  *   Sec. II-B        PILA: per pixel, the (detector position, length) pairs
  *                    of every angle, from a Siddon ray trace; Eq. 6
  *                    (sinogram update) and Eq. 7 (cost update)
+ *   Sec. II-B        one-byte lengths: round(180 l)
  *   Sec. III         Eq. 8 (initial temperature from Q uphill estimates),
  *                    T_N = T_0 / 10^3
+ *   Sec. III-A       the comparison method: SAT whose evaluation step
+ *                    projects the whole image by bilinear interpolation
  *   Sec. III-B       best of multiple estimates (BoME)
- *   Sec. III-D       Eq. 10-11 SIRT with exact lengths and the factor matrix
+ *   Sec. III-C       the exponential schedule (the second Eq. 8) and the
+ *                    cubic one (Eq. 9)
+ *   Sec. III-D       Eq. 10-11 SIRT with exact lengths and the factor matrix,
+ *                    simultaneous and pixel by pixel
  *
  * Readings where the paper is silent (geometry, RNG, clamped proposals,
  * simultaneous SIRT, stage indexing) are stated next to the code that
@@ -33,9 +39,15 @@
  * (Philox against numpy's Philox4x64-10; PILA against brute-force clipping
  * and hand-derived lengths; projection against closed-form chords; Eq. 7
  * against full recomputation of Eq. 4; the chain against an independent
- * replay with dense projection; SIRT against dense Landweber).  The FP32
- * residual mode has no exact pin (it is an approximation by design) and is
- * checked only for bounded drift against its own FP64 resync.
+ * replay with dense projection; SIRT against dense Landweber; the
+ * sequential SIRT against a one-pixel closed form, its weighted-residual
+ * descent and its fixed point; the bilinear DRT against scipy's bilinear
+ * sampling and closed forms; the one-byte lengths against the rounding
+ * bound).  The FP32 residual mode is pinned by rounding-error bounds: each
+ * FP32 row sum against the exact sum of the same float operands, and the
+ * running residual against a from-scratch dense residual (exact to one
+ * float rounding right after a resync, within the accumulated rounding
+ * bound otherwise).
  */
 #include <math.h>
 #include <stdint.h>
@@ -386,6 +398,10 @@ typedef struct {
     double tn_ratio;    /* T_N = T_0 / tn_ratio when T0 is automatic */
     double delta_max, f_min, f_max;
     int64_t resync_every; /* FP32: full FP64 recomputation every so many nonzero accepts */
+    int32_t schedule;     /* 0: Eq. 2 (linear), 1: Sec. III-C's second Eq. 8 (exponential),
+                             2: Eq. 9 (cubic) */
+    int32_t proposal;     /* 0: new value clamped to [f_min, f_max]; 1: redrawn until it
+                             falls inside (Eq. 3 as printed) */
 } or_sat_params;
 
 typedef struct {
@@ -394,13 +410,21 @@ typedef struct {
     double T0_used, TN_used, sse_final, cost_final, max_drift_r, max_drift_sse;
 } or_sat_stats;
 
-/* Temperature of step s under the linear schedule Eq. 2: the n_steps steps
- * are split into n_stages stages of equal length (M repetitions per stage,
- * Sec. II-A), stage n = floor(s * n_stages / n_steps), n = 0 .. n_stages-1. */
-double or_temperature(int64_t s, int64_t n_steps, int32_t n_stages, double T0, double TN)
+/* Temperature of step s.  The n_steps steps are split into n_stages stages
+ * of equal length (M repetitions per stage, Sec. II-A); stage
+ * n = floor(s * n_stages / n_steps), n = 0 .. n_stages-1, and with N the
+ * number of stages:
+ *   schedule 0, Eq. 2:                  T_n = T0 - n (T0 - TN) / N
+ *   schedule 1, Sec. III-C (second (8)): T_n = T0 (TN / T0)^(n / N)
+ *   schedule 2, Eq. 9:                  T_n = T0 - n^3 (T0 - TN) / N^3   */
+double or_temperature(int64_t s, int64_t n_steps, int32_t n_stages, double T0, double TN,
+                      int32_t schedule)
 {
     int64_t n = (s * (int64_t)n_stages) / n_steps;
-    return T0 - (double)n * ((T0 - TN) / (double)n_stages);
+    double x = (double)n, Nn = (double)n_stages;
+    if (schedule == 1) return T0 * pow(TN / T0, x / Nn);
+    if (schedule == 2) return T0 - (x * x * x) * ((T0 - TN) / (Nn * Nn * Nn));
+    return T0 - x * ((T0 - TN) / Nn);
 }
 
 /* Change of the RMS cost C (Eq. 4) when the sum of squared residuals moves
@@ -415,20 +439,38 @@ static double cost_change(double sse, double dS, double KU)
     return (dS / KU) / den;
 }
 
-/* A random single-pixel estimate (Step 2, Eq. 3) drawn from Philox words:
- * pixel uniform over the support, change uniform in [-dmax, dmax), new value
- * clamped to [f_min, f_max] (a clamp instead of the paper's redraw). */
-static void draw_estimate(const uint64_t w[4], int64_t P, const int32_t* support,
-                          const double* f, const or_sat_params* prm, int32_t* p_out,
-                          double* fn_out, double* d_out)
+/* A random single-pixel estimate (Step 2, Eq. 3).  Philox counter
+ * (c0, c1, purpose, 0) gives the pixel (uniform over the support, word 0)
+ * and the change (uniform in [-dmax, dmax), word 1).  A new value outside
+ * [f_min, f_max] is clamped into it (proposal 0), or the change is drawn
+ * again from counter (c0, c1, purpose, j), j = 1, 2, ..., for the same
+ * pixel until the new value falls inside (proposal 1, Eq. 3 as printed);
+ * after OR_REDRAW_MAX draws without success the value stays (change 0). */
+#define OR_REDRAW_MAX 256
+static void draw_estimate(const uint64_t key[2], uint64_t c0, uint64_t c1, uint64_t purpose,
+                          int64_t P, const int32_t* support, const double* f,
+                          const or_sat_params* prm, int32_t* p_out, double* fn_out, double* d_out)
 {
+    uint64_t ctr[4] = {c0, c1, purpose, 0}, w[4];
+    or_philox(key, ctr, w);
     int32_t p = support[uindex(w[0], (uint64_t)P)];
-    double u1 = u01(w[1]);
-    double delta = prm->delta_max * (2.0 * u1 - 1.0);
     double fo = f[p];
+    double delta = prm->delta_max * (2.0 * u01(w[1]) - 1.0);
     double fn = fo + delta;
-    if (fn < prm->f_min) fn = prm->f_min;
-    if (fn > prm->f_max) fn = prm->f_max;
+    if (prm->proposal == 1) {
+        int j = 0;
+        while ((fn < prm->f_min || fn > prm->f_max) && j < OR_REDRAW_MAX) {
+            ++j;
+            ctr[3] = (uint64_t)j;
+            or_philox(key, ctr, w);
+            delta = prm->delta_max * (2.0 * u01(w[1]) - 1.0);
+            fn = fo + delta;
+        }
+        if (fn < prm->f_min || fn > prm->f_max) fn = fo;
+    } else {
+        if (fn < prm->f_min) fn = prm->f_min;
+        if (fn > prm->f_max) fn = prm->f_max;
+    }
     *p_out = p;
     *fn_out = fn;
     *d_out = fn - fo;
@@ -436,7 +478,7 @@ static void draw_estimate(const uint64_t w[4], int64_t P, const int32_t* support
 
 /* Eq. 7's inner sum for one estimate: change of the sum of squared
  * residuals when pixel p changes by d, over the pixel's PILA row. */
-static double delta_sse64(const int64_t* row_ptr, const int32_t* col, const double* len,
+double or_delta_sse64(const int64_t* row_ptr, const int32_t* col, const double* len,
                           const double* r, int32_t p, double d, double* sabs)
 {
     double S = 0.0, A = 0.0;
@@ -450,7 +492,7 @@ static double delta_sse64(const int64_t* row_ptr, const int32_t* col, const doub
     return S;
 }
 
-static float delta_sse32(const int64_t* row_ptr, const int32_t* col, const double* len,
+float or_delta_sse32(const int64_t* row_ptr, const int32_t* col, const double* len,
                          const float* r, int32_t p, double d)
 {
     float S = 0.0f;
@@ -498,13 +540,11 @@ static int auto_t0(const or_sat_params* prm, int64_t P, const int32_t* support,
     int64_t found = 0;
     int64_t limit = 1000 * (int64_t)prm->q_auto;
     for (int64_t q = 0; q < limit && found < prm->q_auto; ++q) {
-        uint64_t ctr[4] = {(uint64_t)q, 0, 2, 0}, w[4];
-        or_philox(key, ctr, w);
         int32_t p;
         double fn, d;
-        draw_estimate(w, P, support, f, prm, &p, &fn, &d);
-        double S = prm->precision ? (double)delta_sse32(row_ptr, col, len, r32, p, d)
-                                  : delta_sse64(row_ptr, col, len, r64, p, d, NULL);
+        draw_estimate(key, (uint64_t)q, 0, 2, P, support, f, prm, &p, &fn, &d);
+        double S = prm->precision ? (double)or_delta_sse32(row_ptr, col, len, r32, p, d)
+                                  : or_delta_sse64(row_ptr, col, len, r64, p, d, NULL);
         double dC = cost_change(sse, S, KU);
         if (dC > 0.0) {
             sum += dC;
@@ -532,13 +572,14 @@ static int auto_t0(const or_sat_params* prm, int64_t P, const int32_t* support,
  * f is the N*N image (in: starting image, out: result).  sino is Pm (U*K).
  * Trace arrays (n_steps each, nullable): chosen estimate, acceptance,
  * Delta C, and the scale sum|terms| / KU / (C' + C) that bounds the
- * rounding of Delta C.  Returns 0, or -1 on bad input, -2 when Eq. 8 finds
+ * rounding of Delta C.  r_out (nullable, U*K) receives the final running
+ * residual (the FP32 one widened, in FP32 mode).  Returns 0, or -1 on bad input, -2 when Eq. 8 finds
  * too few uphill estimates.
  */
 int or_sat_run(int32_t N, int32_t U, int32_t K, const uint8_t* mask, const int64_t* row_ptr,
                const int32_t* col, const double* len, const double* sino,
                const or_sat_params* prm, double* f, or_sat_stats* st, int32_t* tr_m,
-               uint8_t* tr_acc, double* tr_dc, double* tr_scale)
+               uint8_t* tr_acc, double* tr_dc, double* tr_scale, double* r_out)
 {
     const int64_t NP = (int64_t)N * N, G = (int64_t)U * K;
     const double KU = (double)K * (double)U;
@@ -575,17 +616,15 @@ int or_sat_run(int32_t N, int32_t U, int32_t K, const uint8_t* mask, const int64
     double drift_r = 0.0, drift_sse = 0.0;
 
     for (int64_t s = 0; s < prm->n_steps; ++s) {
-        double T = or_temperature(s, prm->n_steps, prm->n_stages, T0, TN);
+        double T = or_temperature(s, prm->n_steps, prm->n_stages, T0, TN, prm->schedule);
         int32_t best_m = -1, best_p = 0;
         double best_S = INFINITY, best_fn = 0.0, best_d = 0.0, best_abs = 0.0;
         for (int32_t m = 0; m < prm->m_cand; ++m) {
-            uint64_t ctr[4] = {(uint64_t)s, (uint64_t)m, 0, 0}, w[4];
-            or_philox(key, ctr, w);
             int32_t p;
             double fn, d, sabs = 0.0;
-            draw_estimate(w, P, support, f, prm, &p, &fn, &d);
-            double S = f32 ? (double)delta_sse32(row_ptr, col, len, r32, p, d)
-                           : delta_sse64(row_ptr, col, len, r64, p, d, &sabs);
+            draw_estimate(key, (uint64_t)s, (uint64_t)m, 0, P, support, f, prm, &p, &fn, &d);
+            double S = f32 ? (double)or_delta_sse32(row_ptr, col, len, r32, p, d)
+                           : or_delta_sse64(row_ptr, col, len, r64, p, d, &sabs);
             if (S < best_S || best_m < 0) {
                 best_S = S;
                 best_m = m;
@@ -649,6 +688,8 @@ int or_sat_run(int32_t N, int32_t U, int32_t K, const uint8_t* mask, const int64
         st->max_drift_r = drift_r;
         st->max_drift_sse = drift_sse;
     }
+    if (r_out)
+        for (int64_t g = 0; g < G; ++g) r_out[g] = f32 ? (double)r32[g] : r64[g];
     free(support);
     free(r64);
     free(r32);
@@ -695,4 +736,208 @@ int or_sirt_run(int32_t N, int32_t U, int32_t K, const int64_t* row_ptr, const i
     free(W);
     free(res);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SIRT with exact lengths, pixel by pixel (Sec. III-D as described)        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Sequential form of Eq. 10-11: the factor matrix W_g = sum over support
+ * pixels of l(p, g)^2 is computed once and the calculated projections
+ * Pc = A f once; then n_iter times, m_per times: a support pixel p is chosen
+ * (Philox key (seed, 0), counter (n * m_per + m, 0, 3, 0), uniform over the
+ * support as the annealing chain chooses pixels), it moves by
+ * (lambda / U) * sum over its PILA row of l * (Pm_g - Pc_g) / W_g (rays with
+ * W_g = 0 add nothing; lambda = 1 is the formula as printed), and its rays'
+ * calculated projections get Eq. 6 with that change.  cost[n] (nullable)
+ * receives Eq. 4 of the running projections after iteration n.  f is the
+ * N*N image (in: start, out: result); support holds the P support pixels.
+ */
+int or_sirt_seq_run(int32_t N, int32_t U, int32_t K, const int64_t* row_ptr, const int32_t* col,
+                    const double* len, const double* sino, int64_t P, const int32_t* support,
+                    int32_t n_iter, int64_t m_per, double lambda, uint64_t seed, double* f,
+                    double* cost)
+{
+    const int64_t NP = (int64_t)N * N, G = (int64_t)U * K;
+    const double KU = (double)K * (double)U;
+    if (P < 1 || n_iter < 0 || m_per < 0) return -1;
+    double* W = (double*)calloc((size_t)G, sizeof(double));
+    double* Pc = (double*)malloc(sizeof(double) * (size_t)G);
+    for (int64_t p = 0; p < NP; ++p)
+        for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) W[col[e]] += len[e] * len[e];
+    or_forward(N, U, K, row_ptr, col, len, f, Pc);
+    const uint64_t key[2] = {seed, 0};
+    for (int32_t n = 0; n < n_iter; ++n) {
+        for (int64_t m = 0; m < m_per; ++m) {
+            uint64_t ctr[4] = {(uint64_t)n * (uint64_t)m_per + (uint64_t)m, 0, 3, 0}, w[4];
+            or_philox(key, ctr, w);
+            int32_t p = support[uindex(w[0], (uint64_t)P)];
+            double a = 0.0;
+            for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e)
+                if (W[col[e]] > 0.0) a += len[e] * (sino[col[e]] - Pc[col[e]]) / W[col[e]];
+            double df = (lambda / (double)U) * a;
+            f[p] = f[p] + df;
+            for (int64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) Pc[col[e]] += df * len[e];
+        }
+        if (cost) {
+            double sse = 0.0;
+            for (int64_t g = 0; g < G; ++g) sse += (Pc[g] - sino[g]) * (Pc[g] - sino[g]);
+            cost[n] = sqrt(sse / KU);
+        }
+    }
+    free(W);
+    free(Pc);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The projector the PILA replaces: DRT by bilinear interpolation (Sec.     */
+/* III-A's comparison method), and annealing with it                        */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear interpolation of the image at (x, y): pixel (i, j) holds its
+ * value at its centre (j - N/2 + 1/2, N/2 - 1/2 - i); outside the grid the
+ * image is zero.  With ov_p >= 0 pixel ov_p reads ov_v instead. */
+static double bilinear(int32_t N, const double* f, double x, double y, int64_t ov_p, double ov_v)
+{
+    const double h = N / 2.0;
+    double cx = x + h - 0.5, cy = h - 0.5 - y; /* column and row coordinates */
+    double j0 = floor(cx), i0 = floor(cy);
+    double ax = cx - j0, ay = cy - i0;
+    double v = 0.0;
+    for (int di = 0; di < 2; ++di)
+        for (int dj = 0; dj < 2; ++dj) {
+            double i = i0 + di, j = j0 + dj;
+            if (i < 0 || j < 0 || i >= N || j >= N) continue;
+            int64_t p = (int64_t)i * N + (int64_t)j;
+            double fv = (p == ov_p) ? ov_v : f[p];
+            double wgt = (di ? ay : 1.0 - ay) * (dj ? ax : 1.0 - ax);
+            v += wgt * fv;
+        }
+    return v;
+}
+
+/* Samples per ray of the DRT: unit spacing t = -T .. T along the ray with
+ * T = ceil(N / sqrt 2) + 1, which covers every point where the bilinear
+ * image can be nonzero. */
+int32_t or_drt_half_span(int32_t N) { return (int32_t)ceil(N / sqrt(2.0)) + 1; }
+
+/* DRT of one ray (u, k): the sum of bilinear samples at unit steps along
+ * x cos + y sin = s_k, i.e. the points (s c - t sn, s sn + t c). */
+static double drt_ray(int32_t N, int32_t K, const double* cs, int32_t u, int32_t k, const double* f,
+                      int64_t ov_p, double ov_v)
+{
+    const double c = cs[2 * u], sn = cs[2 * u + 1];
+    const double s = k - (K - 1) / 2.0;
+    const int32_t T = or_drt_half_span(N);
+    double acc = 0.0;
+    for (int32_t t = -T; t <= T; ++t) acc += bilinear(N, f, s * c - t * sn, s * sn + t * c, ov_p, ov_v);
+    return acc;
+}
+
+/* Eq. 1 computed the conventional way: out[u*K + k] is the DRT of ray
+ * (u, k) of image f by bilinear interpolation. */
+void or_drt(int32_t N, int32_t U, int32_t K, const double* deg, const double* f, double* out)
+{
+    double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)U);
+    or_trig(U, deg, cs);
+    for (int32_t u = 0; u < U; ++u)
+        for (int32_t k = 0; k < K; ++k) out[(int64_t)u * K + k] = drt_ray(N, K, cs, u, k, f, -1, 0.0);
+    free(cs);
+}
+
+/*
+ * SAT with the DRT in the evaluation step (Steps 1-4 of Sec. II-A without
+ * the PILA): every estimate's image is projected in full by the bilinear
+ * DRT and its cost C' taken from Eq. 4 directly; the first estimate of
+ * least C' is kept (BoME); Delta C = C' - C decides acceptance as in
+ * or_sat_run, with the same estimates, temperatures and acceptance
+ * uniforms (Philox counters (s, m, 0, 0) and (s, 0, 1, 0)).  T0 and TN are
+ * given.  Trace arrays (nullable, n_steps each): chosen estimate,
+ * acceptance, Delta C.  Returns 0, or -1 on bad input.
+ */
+int or_satdrt_run(int32_t N, int32_t U, int32_t K, const double* deg, const uint8_t* mask,
+                  const double* sino, const or_sat_params* prm, double* f, int32_t* tr_m,
+                  uint8_t* tr_acc, double* tr_dc, double* cost_final)
+{
+    const int64_t NP = (int64_t)N * N;
+    const double KU = (double)K * (double)U;
+    if (prm->m_cand < 1 || prm->n_steps < 0 || prm->n_stages < 1 || !(prm->T0 > 0.0)) return -1;
+    int64_t P = 0;
+    for (int64_t p = 0; p < NP; ++p) P += (!mask || mask[p]) ? 1 : 0;
+    if (P == 0) return -1;
+    int32_t* support = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+    P = 0;
+    for (int64_t p = 0; p < NP; ++p)
+        if (!mask || mask[p]) support[P++] = (int32_t)p;
+    double* cs = (double*)malloc(sizeof(double) * 2 * (size_t)U);
+    or_trig(U, deg, cs);
+    /* Eq. 4 of an image (with one pixel overridden) through the full DRT */
+#define OR_DRT_COST(OVP, OVV, OUT)                                                  \
+    do {                                                                            \
+        double sse_ = 0.0;                                                          \
+        for (int32_t u_ = 0; u_ < U; ++u_)                                          \
+            for (int32_t k_ = 0; k_ < K; ++k_) {                                    \
+                double d_ = drt_ray(N, K, cs, u_, k_, f, (OVP), (OVV)) -            \
+                            sino[(int64_t)u_ * K + k_];                             \
+                sse_ += d_ * d_;                                                    \
+            }                                                                       \
+        (OUT) = sqrt(sse_ / KU);                                                    \
+    } while (0)
+    double C;
+    OR_DRT_COST(-1, 0.0, C);
+    const uint64_t key[2] = {prm->seed, prm->chain_id};
+    for (int64_t s = 0; s < prm->n_steps; ++s) {
+        double T = or_temperature(s, prm->n_steps, prm->n_stages, prm->T0, prm->TN, prm->schedule);
+        int32_t best_m = -1, best_p = 0;
+        double best_C = INFINITY, best_fn = 0.0;
+        for (int32_t m = 0; m < prm->m_cand; ++m) {
+            int32_t p;
+            double fn, d, Cm;
+            draw_estimate(key, (uint64_t)s, (uint64_t)m, 0, P, support, f, prm, &p, &fn, &d);
+            OR_DRT_COST(p, fn, Cm);
+            if (Cm < best_C || best_m < 0) {
+                best_C = Cm;
+                best_m = m;
+                best_p = p;
+                best_fn = fn;
+            }
+        }
+        double dC = best_C - C;
+        uint64_t actr[4] = {(uint64_t)s, 0, 1, 0}, aw[4];
+        or_philox(key, actr, aw);
+        double N1 = u01(aw[0]);
+        int accept = (dC <= 0.0) || (N1 < exp(-dC / T));
+        if (tr_m) tr_m[s] = best_m;
+        if (tr_acc) tr_acc[s] = (uint8_t)accept;
+        if (tr_dc) tr_dc[s] = dC;
+        if (accept) {
+            f[best_p] = best_fn;
+            C = best_C;
+        }
+    }
+#undef OR_DRT_COST
+    if (cost_final) *cost_final = C;
+    free(support);
+    free(cs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-byte lengths (Sec. II-B: length x 180, rounded)                       */
+/* ------------------------------------------------------------------------ */
+
+/* q = round(180 l) (halves away from zero) for each of n lengths; every
+ * length lies in [0, sqrt 2], so q fits one byte (at most 255). */
+void or_quantize_u8(int64_t n, const double* len, uint8_t* q)
+{
+    for (int64_t i = 0; i < n; ++i) q[i] = (uint8_t)lround(180.0 * len[i]);
+}
+
+/* The length a one-byte entry stands for, q / 180, as a float (the type the
+ * residual arithmetic of an FP32 chain uses), widened to double. */
+void or_dequantize_u8(int64_t n, const uint8_t* q, double* len)
+{
+    for (int64_t i = 0; i < n; ++i) len[i] = (double)((float)q[i] / 180.0f);
 }
