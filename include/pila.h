@@ -52,6 +52,24 @@ extern "C" {
 #define PILA_F64 0
 #define PILA_F32 1
 
+/* cooling schedules (sat_params.schedule), section II-A and III-C */
+#define PILA_SCHED_LINEAR 0 /* Eq. 2:  T_n = T0 - n (T0 - TN) / N */
+#define PILA_SCHED_EXP 1    /* the faster drop of section III-C (its second Eq. 8):
+                               T_n = T0 (TN / T0)^(n / N) */
+#define PILA_SCHED_CUBIC 2  /* Eq. 9:  T_n = T0 - n^3 (T0 - TN) / N^3 */
+
+/* what happens to a proposed value outside [f_min, f_max] (sat_params.proposal) */
+#define PILA_PROP_CLAMP 0   /* clamped into the range */
+#define PILA_PROP_REDRAW 1  /* the change is drawn again until the value is in range
+                               (Step 2, Eq. 3 as printed) */
+
+/* which chain body ran a chain (sat_stats.body): a kind plus flags */
+#define PILA_BODY_PIPED 1     /* rows in registers, estimates drawn ahead */
+#define PILA_BODY_LONG 2      /* rows of more than 512 entries, one estimate per wavefront */
+#define PILA_BODY_GENERAL 3   /* any row length and M, draws at the step (needed for redraw) */
+#define PILA_BODY_GLOBAL_R 16 /* flag: the residual lives (partly) in global memory */
+#define PILA_BODY_SEGMENTED 32 /* flag: FP32 resyncs ran grid-wide between launches */
+
 /* ------------------------------------------------------------------------ */
 /* Geometry and the PILA (section II-B, Eq. 5)                               */
 /* ------------------------------------------------------------------------ */
@@ -92,21 +110,31 @@ typedef struct pila_csr {
 } pila_csr;
 
 /*
+ * pila_build_scratch_size - device scratch bytes pila_build needs for this
+ * geometry (the mask and a few scalars): N*N + 256.
+ */
+int32_t pila_build_scratch_size(const pila_geom* geom, size_t* bytes);
+
+/*
  * pila_build - intersection lengths of every support pixel with every ray
  * (section II-B: per pixel, the detector positions and lengths at each
  * angle, Eq. 5), stored pixel-major and ray-major.
  *
  * Two phases.  Phase 1 (csr->col == NULL): needs csr->row_ptr, csr->trig
  * and csr->t_row_ptr; fills them, sets csr->nnz, csr->n_support,
- * csr->max_row and csr->k_lo/k_hi, and synchronises the stream.  pila_build allocates and
- * frees a temporary device buffer of N*N + 256 bytes during each phase.  Phase 2 (csr->col != NULL): needs every array,
- * sized from phase 1; row_ptr/t_row_ptr must still hold phase 1's output.
- * Fills col, len, support, t_col, t_len and synchronises.
- * Errors: EINVAL for n, U or K < 1, a non-finite angle, a NULL array, or
- * len_dtype not PILA_F64/PILA_F32; ESIZE when phase 2's row_ptr total does
- * not equal csr->nnz; EHIP on a runtime failure.
+ * csr->max_row and csr->k_lo/k_hi, and synchronises the stream.  Phase 2
+ * (csr->col != NULL): needs every array, sized from phase 1;
+ * row_ptr/t_row_ptr must still hold phase 1's output.  Fills col, len,
+ * support, t_col, t_len and synchronises.  d_scratch is caller device
+ * memory of at least pila_build_scratch_size bytes, used during the call
+ * only; the library allocates no device memory.
+ * Errors: EINVAL for n, U or K < 1, a non-finite angle, a NULL array or
+ * scratch, or len_dtype not PILA_F64/PILA_F32; ENOMEM when scratch_bytes
+ * is too small; ESIZE when phase 2's row_ptr total does not equal
+ * csr->nnz; EHIP on a runtime failure.
  */
-int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream);
+int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* d_scratch, size_t scratch_bytes,
+                   void* stream);
 
 /*
  * pila_forward - Eq. 1 for every ray: d_out[g] = sum over pixels of
@@ -140,9 +168,13 @@ typedef struct sat_params {
     int32_t precision;   /* PILA_F64 or PILA_F32 residual sinogram */
     double tn_ratio;     /* T_N = T_0 / tn_ratio when Eq. 8 is used */
     double delta_max;    /* Eq. 3 step: change uniform in [-delta_max, delta_max) */
-    double f_min, f_max; /* value range; a new value is clamped into it */
+    double f_min, f_max; /* value range of a pixel */
     int64_t resync_every; /* FP32: FP64 recomputation of the residual after
                              this many accepted nonzero changes; 0 = never */
+    int32_t schedule;     /* PILA_SCHED_LINEAR, _EXP or _CUBIC */
+    int32_t proposal;     /* PILA_PROP_CLAMP or PILA_PROP_REDRAW (redraws use counter
+                             (s, m, 0, j) for the j-th redraw, at most 256, after which
+                             the value stays; chains that redraw run the general body) */
 } sat_params;
 
 typedef struct sat_stats {
@@ -156,7 +188,7 @@ typedef struct sat_stats {
     double max_drift_sse;   /* FP32: max relative |SSE_run - SSE64| at a resync */
     int32_t chain_launches; /* sat_run: launches of the chain kernel (one, or one
                                per resync segment); 0 from sat_run_batch */
-    int32_t pad;
+    int32_t body;           /* PILA_BODY_* kind | flags of the body that ran the chain */
     double chain_kernel_ms; /* sat_run: summed duration of those launches, from
                                HIP events recorded around each of them */
 } sat_stats;
@@ -182,7 +214,8 @@ int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size
  *   Philox counter (q, 0, 2, 0));
  *   for step s: m_cand estimates (Philox4x64-10, key (seed, chain_id),
  *   counter (s, m, 0, 0)): pixel uniform over the support, change uniform
- *   in [-delta_max, delta_max), new value clamped to [f_min, f_max]; each
+ *   in [-delta_max, delta_max), new value clamped to [f_min, f_max] or
+ *   redrawn (params.proposal); each
  *   scored by the change of the squared-residual sum over its PILA row
  *   (Eq. 7); the first minimum is kept (BoME); accepted when its cost
  *   change Delta C <= 0 or N1 < exp(-Delta C / T) (Step 4; N1 from counter
@@ -222,8 +255,10 @@ typedef struct sat_launch {
  * per slice) in one persistent launch: one workgroup runs one chain at a
  * time and takes the next chain from a device ticket counter.  Each chain
  * computes exactly what sat_run computes for its job, independently of the
- * other jobs and of the launch shape's chain placement.  h_stats [n_jobs]
- * (nullable) makes the call synchronise.
+ * other jobs and of the launch shape's chain placement.  The call uploads
+ * the chain descriptors from host memory it owns and synchronises the
+ * stream before it returns, whether or not h_stats [n_jobs] (nullable)
+ * asks for the statistics.
  */
 int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs, size_t* bytes);
 int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch, void* d_ws,

@@ -20,8 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libpila.so")
 PILA_OK, PILA_EINVAL, PILA_ENOMEM, PILA_EHIP, PILA_ESIZE = 0, -1, -2, -3, -4
 PILA_ECANCELED, PILA_EBUSY, PILA_ENOTFOUND = -5, -6, -7
 PILA_F64, PILA_F32 = 0, 1
+SCHEDULES = {"linear": 0, "exp": 1, "cubic": 2}      # PILA_SCHED_*
+PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
+BODY_PIPED, BODY_LONG, BODY_GENERAL = 1, 2, 3         # PILA_BODY_* kinds
+BODY_GLOBAL_R, BODY_SEGMENTED = 16, 32                # PILA_BODY_* flags
 
-EXPORTED = ["pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run",
+EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run",
             "sat_batch_workspace_size", "sat_run_batch", "sirt_workspace_size", "sirt_run",
             "srv_create", "srv_prepare", "srv_submit", "srv_poll", "srv_cancel", "srv_get_status",
             "srv_destroy", "pila_get_device_info", "pila_last_error"]
@@ -50,7 +54,8 @@ class CSatParams(C.Structure):
                 ("n_stages", C.c_int32), ("m_cand", C.c_int32), ("T0", C.c_double),
                 ("TN", C.c_double), ("q_auto", C.c_int32), ("precision", C.c_int32),
                 ("tn_ratio", C.c_double), ("delta_max", C.c_double), ("f_min", C.c_double),
-                ("f_max", C.c_double), ("resync_every", C.c_int64)]
+                ("f_max", C.c_double), ("resync_every", C.c_int64), ("schedule", C.c_int32),
+                ("proposal", C.c_int32)]
 
 
 class CSatStats(C.Structure):
@@ -58,7 +63,7 @@ class CSatStats(C.Structure):
                 ("resyncs", C.c_int32), ("status", C.c_int32), ("T0_used", C.c_double),
                 ("TN_used", C.c_double), ("sse_final", C.c_double), ("cost_final", C.c_double),
                 ("max_drift_r", C.c_double), ("max_drift_sse", C.c_double),
-                ("chain_launches", C.c_int32), ("pad", C.c_int32), ("chain_kernel_ms", C.c_double)]
+                ("chain_launches", C.c_int32), ("body", C.c_int32), ("chain_kernel_ms", C.c_double)]
 
 
 class CSatTrace(C.Structure):
@@ -115,7 +120,8 @@ def load(path: str = LIB_PATH):
     lib = C.CDLL(path)
     V, I32 = C.c_void_p, C.c_int32
     G, CS = C.POINTER(CGeom), C.POINTER(CCsr)
-    lib.pila_build.argtypes = [G, CS, V]
+    lib.pila_build_scratch_size.argtypes = [G, C.POINTER(C.c_size_t)]
+    lib.pila_build.argtypes = [G, CS, V, C.c_size_t, V]
     lib.pila_forward.argtypes = [G, CS, V, V, V]
     lib.pila_backproject.argtypes = [G, CS, V, V, V]
     lib.sat_workspace_size.argtypes = [G, C.POINTER(CSatParams), C.POINTER(C.c_size_t)]
@@ -229,7 +235,11 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     trig = torch.empty(2 * U, dtype=torch.float64, device=dev)
     csr = CCsr(0, 0, 0, 0, -1, row_ptr.data_ptr(), None, None, None, trig.data_ptr(),
                t_row_ptr.data_ptr(), None, None)
-    _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
+    nb = C.c_size_t(0)
+    _check(lib.pila_build_scratch_size(C.byref(geom.c), C.byref(nb)))
+    scratch = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    _check(lib.pila_build(C.byref(geom.c), C.byref(csr), scratch.data_ptr(), scratch.numel(),
+                          _stream()))
     nnz, P, max_row = int(csr.nnz), int(csr.n_support), int(csr.max_row)
     k_lo, k_hi = int(csr.k_lo), int(csr.k_hi)
     ldt = torch.float64 if geom.len_dtype == PILA_F64 else torch.float32
@@ -241,7 +251,8 @@ def pila_build(geom: Geometry, device=None) -> Pila:
     csr.col, csr.len, csr.t_col, csr.t_len, csr.support = (col.data_ptr(), ln.data_ptr(),
                                                            t_col.data_ptr(), t_ln.data_ptr(),
                                                            support.data_ptr())
-    _check(lib.pila_build(C.byref(geom.c), C.byref(csr), _stream()))
+    _check(lib.pila_build(C.byref(geom.c), C.byref(csr), scratch.data_ptr(), scratch.numel(),
+                          _stream()))
     return Pila(geom, dict(row_ptr=row_ptr, col=col[:nnz], len=ln[:nnz], support=support[:P],
                            trig=trig, t_row_ptr=t_row_ptr, t_col=t_col[:nnz], t_len=t_ln[:nnz]),
                 nnz, P, max_row, k_lo, k_hi)
@@ -293,12 +304,15 @@ class SatParams:
     f_min: float = 0.0
     f_max: float = 1.0
     resync_every: int = 0
+    schedule: str = "linear"        # "linear" (Eq. 2), "exp" (section III-C), "cubic" (Eq. 9)
+    proposal: str = "clamp"         # "clamp", or "redraw" (Eq. 3 as printed)
 
     def c(self) -> CSatParams:
         return CSatParams(self.seed, self.chain_id, self.n_steps, self.n_stages, self.m_cand,
                           self.T0 or 0.0, self.TN or 0.0, self.q_auto,
                           PILA_F32 if self.precision in ("f32", PILA_F32) else PILA_F64,
-                          self.tn_ratio, self.delta_max, self.f_min, self.f_max, self.resync_every)
+                          self.tn_ratio, self.delta_max, self.f_min, self.f_max, self.resync_every,
+                          SCHEDULES[self.schedule], PROPOSALS[self.proposal])
 
 
 def _stats_dict(s: CSatStats) -> dict:

@@ -220,14 +220,6 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t* __restrict__ a, int
     }
 }
 
-struct DeviceBuffer {
-    void* p = nullptr;
-    ~DeviceBuffer()
-    {
-        if (p) (void)hipFree(p);
-    }
-};
-
 unsigned blocks_for(int64_t items) { return (unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock); }
 
 template <typename LenT>
@@ -249,16 +241,28 @@ using namespace pila;
 
 size_t pila::pila_build_scratch(const pila_geom* geom) { return 256 + (size_t)geom->n * (size_t)geom->n; }
 
-extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* stream)
+extern "C" int32_t pila_build_scratch_size(const pila_geom* geom, size_t* bytes)
+{
+    clear_error();
+    PILA_TRY(check_geom(geom));
+    if (!bytes) return fail(PILA_EINVAL, "bytes is NULL");
+    *bytes = pila_build_scratch(geom);
+    return PILA_OK;
+}
+
+extern "C" int32_t pila_build(const pila_geom* geom, pila_csr* csr, void* d_scratch, size_t scratch_bytes,
+                              void* stream)
 {
     clear_error();
     PILA_TRY(check_geom(geom));
     if (!csr) return fail(PILA_EINVAL, "csr is NULL");
     if (!csr->row_ptr || !csr->trig || !csr->t_row_ptr)
         return fail(PILA_EINVAL, "row_ptr, trig and t_row_ptr must be allocated");
-    DeviceBuffer tmp;
-    PILA_HIP(hipMalloc(&tmp.p, pila_build_scratch(geom)));
-    return pila_build_with(geom, csr, tmp.p, (hipStream_t)stream);
+    if (!d_scratch) return fail(PILA_EINVAL, "scratch is NULL");
+    if (scratch_bytes < pila_build_scratch(geom))
+        return fail(PILA_ENOMEM, "scratch of %zu bytes is below the %zu needed", scratch_bytes,
+                    pila_build_scratch(geom));
+    return pila_build_with(geom, csr, d_scratch, (hipStream_t)stream);
 }
 
 int32_t pila::pila_build_with(const pila_geom* geom, pila_csr* csr, void* d_scratch, hipStream_t st)

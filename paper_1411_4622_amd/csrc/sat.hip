@@ -43,6 +43,10 @@ int32_t check_params(const pila_geom* g, const pila_csr* c, const sat_params* p)
     if (!(p->delta_max >= 0.0) || !std::isfinite(p->delta_max) || !(p->f_max >= p->f_min))
         return fail(PILA_EINVAL, "bad delta_max / value range");
     if (p->resync_every < 0) return fail(PILA_EINVAL, "resync_every < 0");
+    if (p->schedule != PILA_SCHED_LINEAR && p->schedule != PILA_SCHED_EXP && p->schedule != PILA_SCHED_CUBIC)
+        return fail(PILA_EINVAL, "schedule must be PILA_SCHED_LINEAR, _EXP or _CUBIC");
+    if (p->proposal != PILA_PROP_CLAMP && p->proposal != PILA_PROP_REDRAW)
+        return fail(PILA_EINVAL, "proposal must be PILA_PROP_CLAMP or PILA_PROP_REDRAW");
     return PILA_OK;
 }
 
@@ -81,11 +85,11 @@ ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, con
     J.sino = sino;
     J.f = image;
     J.max_row = c->max_row;
-    J.pad = 0;
+    J.schedule = p->schedule;
     J.k_lo = c->k_lo;
     J.Kc = c->k_hi >= c->k_lo ? c->k_hi - c->k_lo + 1 : 0;
     J.UL = 0;
-    J.pad2 = 0;
+    J.proposal = p->proposal;
     // g / K for g < 2^24 as (g * m) >> (24 + L), L = ceil(log2 K), m = ceil(2^(24+L) / K):
     // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K
     {
@@ -313,7 +317,7 @@ __global__ void sat_final_kernel(ChainJob job)
     st.max_drift_r = c.drift_r;
     st.max_drift_sse = c.drift_sse;
     st.chain_launches = 0;
-    st.pad = 0;
+    st.body = 0;
     st.chain_kernel_ms = 0.0;
     *job.stats = st;
 }
@@ -565,12 +569,14 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     const bool r_in_lds = G * rs <= budget;
     const int table_lds = (int)hybrid_lds(&J, budget);
     int waves = 0;
-    const PipedShape* ps =
-        piped_allowed(geom, csr) ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
-                                 : nullptr;
+    // redrawn proposals depend on the image value at the step: general body only
+    const bool ahead = params->proposal == PILA_PROP_CLAMP;
+    const PipedShape* ps = ahead && piped_allowed(geom, csr)
+                               ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
+                               : nullptr;
     const bool resync = params->precision == PILA_F32 && params->resync_every > 0;
     // rows too long for the pipelined body's registers: the long-row body
-    const bool lng = !ps && long_allowed(geom, csr, params);
+    const bool lng = ahead && !ps && long_allowed(geom, csr, params);
     const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
     // the pipelined body in global mode takes the entries' slot words
     // precomputed when the workspace has room for them
@@ -585,7 +591,11 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     }
     const bool long_seg = lng && !r_in_lds && resync;
     const bool simple_seg = !ps && !lng && !r_in_lds && resync;
+    const int glob = r_in_lds ? 0 : PILA_BODY_GLOBAL_R;
+    int body = 0;
     if (piped_seg || long_seg || simple_seg) {
+        body = (piped_seg ? PILA_BODY_PIPED : long_seg ? PILA_BODY_LONG : PILA_BODY_GENERAL) |
+               PILA_BODY_GLOBAL_R | PILA_BODY_SEGMENTED;
         // FP32 residual in global memory: chain segments end at each resync,
         // which runs grid-wide; the host only enqueues, it never waits
         const int T = (int)((G + 63) / 64);
@@ -611,10 +621,12 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         }
         sat_final_kernel<<<1, 1, 0, st>>>(J);
     } else if (ps && (r_in_lds || table_lds <= budget)) {
+        body = PILA_BODY_PIPED | glob;
         const int lds = r_in_lds ? (int)(G * rs) : table_lds;
         PILA_TRY(launch1(r_in_lds ? ps->k_lds : (tk ? ps->k_glob_tk : ps->k_glob), &J, waves * kWave, lds, st,
                          &tm));
     } else if (lng) {
+        body = PILA_BODY_LONG | glob;
         const int lds = r_in_lds ? (int)(G * rs) : (int)long_lds(&J, budget);
         ChainKernel k;
         if (params->precision == PILA_F64)
@@ -623,6 +635,7 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
             k = r_in_lds ? sat_long_kernel<float, true, kLongE> : sat_long_kernel<float, false, kLongE>;
         PILA_TRY(launch1(k, &J, params->m_cand * kWave, lds, st, &tm));
     } else {
+        body = PILA_BODY_GENERAL | glob;
         waves = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         const int lds = r_in_lds ? (int)(G * rs) : 0;
         if (params->precision == PILA_F64) {
@@ -641,6 +654,7 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         PILA_HIP(hipMemcpyAsync(h_stats, J.stats, sizeof(sat_stats), hipMemcpyDeviceToHost, st));
         PILA_HIP(hipStreamSynchronize(st));
         h_stats->chain_launches = (int32_t)(tm.ev.size() / 2);
+        h_stats->body = body;
         PILA_TRY(tm.total_ms(&h_stats->chain_kernel_ms));
     }
     return PILA_OK;
@@ -739,14 +753,15 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     std::vector<int> piped_ids, long_ids, simple_ids;
     for (int32_t j = 0; j < n_jobs; ++j) {
         ChainJob& J = host[j];
-        bool ok = bs && J.precision == PILA_F32 && piped_allowed(jobs[j].geom, jobs[j].csr) &&
+        const bool ahead = J.proposal == PILA_PROP_CLAMP;
+        bool ok = ahead && bs && J.precision == PILA_F32 && piped_allowed(jobs[j].geom, jobs[j].csr) &&
                   J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw;
         if (ok) ok = hybrid_lds(&J, lds) <= lds;  // LDS part of the residual
         if (ok) {
             piped_ids.push_back(j);
             continue;
         }
-        if (J.precision == PILA_F32 && waves * kWave <= kPipedThreads && J.m_cand <= waves &&
+        if (ahead && J.precision == PILA_F32 && waves * kWave <= kPipedThreads && J.m_cand <= waves &&
             long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
             long_lds(&J, lds);
             long_ids.push_back(j);
@@ -829,5 +844,14 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     }
     // the descriptor upload reads host memory owned by this call
     PILA_HIP(hipStreamSynchronize(st));
+    if (h_stats) {
+        for (int j : piped_ids) h_stats[j].body = PILA_BODY_PIPED | PILA_BODY_GLOBAL_R;
+        for (int j : long_ids) h_stats[j].body = PILA_BODY_LONG | PILA_BODY_GLOBAL_R;
+        for (int j : simple_ids) {
+            const ChainJob& J = host[j];
+            const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
+            h_stats[j].body = PILA_BODY_GENERAL | (rb <= lds ? 0 : PILA_BODY_GLOBAL_R);
+        }
+    }
     return PILA_OK;
 }

@@ -53,8 +53,9 @@ struct ChainCarry {
 struct ChainJob {
     int32_t N, U, K, P;
     int32_t precision, m_cand, n_stages, q_auto;
-    int32_t max_row, pad;
-    int32_t k_lo, Kc, UL, pad2;  // LDS part of the residual: angles u < UL, bins k_lo .. k_lo+Kc-1
+    int32_t max_row, schedule;   // schedule: PILA_SCHED_* cooling law
+    int32_t k_lo, Kc, UL, proposal;  // LDS part of the residual: angles u < UL, bins k_lo ..
+                                     // k_lo+Kc-1; proposal: PILA_PROP_* (clamp or redraw)
     uint32_t kdiv_m, kdiv_s;     // g / K = (g * kdiv_m) >> kdiv_s for g < 2^24
     int64_t n_steps, resync_every;
     uint64_t seed, chain_id;
@@ -83,6 +84,8 @@ struct ChainJob {
 
 constexpr int kMaxCand = 64;
 constexpr int kMaxWaves = 16;
+// redraws of one estimate's change before it is given up (change 0)
+constexpr uint64_t kRedrawMax = 256;
 
 struct ChainShared {
     double S[kMaxCand];
@@ -129,7 +132,7 @@ __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
     ChainJob J;
 #define PILA_F(f) J.f = lane0(d.f);
     PILA_F(N) PILA_F(U) PILA_F(K) PILA_F(P) PILA_F(precision) PILA_F(m_cand) PILA_F(n_stages)
-    PILA_F(q_auto) PILA_F(max_row) PILA_F(pad) PILA_F(k_lo) PILA_F(Kc) PILA_F(UL) PILA_F(pad2)
+    PILA_F(q_auto) PILA_F(max_row) PILA_F(schedule) PILA_F(k_lo) PILA_F(Kc) PILA_F(UL) PILA_F(proposal)
     PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
     PILA_F(T0) PILA_F(TN) PILA_F(tn_ratio) PILA_F(delta_max) PILA_F(f_min) PILA_F(f_max) PILA_F(ln09)
     PILA_F(row_ptr) PILA_F(col) PILA_F(len) PILA_F(t_row_ptr) PILA_F(t_col) PILA_F(t_len)
@@ -266,20 +269,37 @@ __device__ __forceinline__ double uniform_f64(double v)
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
-// schedule (Eq. 2): stage n = floor(s n_stages / n_steps), tracked
-// incrementally without a 64-bit division per step
+// cooling schedule: stage n = floor(s n_stages / n_steps), tracked
+// incrementally without a 64-bit division per step; with N = n_stages,
+//   Eq. 2 (linear):                        T_n = T0 - n (T0 - TN) / N
+//   exponential (section III-C, 2nd Eq. 8): T_n = T0 (TN / T0)^(n / N)
+//   cubic (Eq. 9):                          T_n = T0 - n^3 (T0 - TN) / N^3
 // ---------------------------------------------------------------------------
 struct Schedule {
     int64_t stage, next;  // current stage, first step of the following stage
-    double T0, dT;
+    double T0, TN, dT, NN;
+    int kind;
     double T, invT;  // temperature of the current stage and its reciprocal
-    __device__ void start(int64_t s, int64_t n_steps, int32_t n_stages, double t0, double tn)
+    __device__ void start(int64_t s, int64_t n_steps, int32_t n_stages, double t0, double tn, int k)
     {
         T0 = t0;
-        dT = (t0 - tn) / (double)n_stages;
+        TN = tn;
+        kind = k;
+        NN = (double)n_stages;
+        dT = (t0 - tn) / NN;
         stage = n_steps > 0 ? (s * (int64_t)n_stages) / n_steps : 0;
         next = first_of(stage + 1, n_steps, n_stages);
-        T = T0 - (double)stage * dT;
+        set();
+    }
+    __device__ void set()
+    {
+        const double x = (double)stage;
+        if (kind == PILA_SCHED_EXP)
+            T = T0 * pow(TN / T0, x / NN);
+        else if (kind == PILA_SCHED_CUBIC)
+            T = T0 - (x * x * x) * ((T0 - TN) / (NN * NN * NN));
+        else
+            T = T0 - x * dT;
         invT = 1.0 / T;
     }
     __device__ static int64_t first_of(int64_t k, int64_t n_steps, int32_t n_stages)
@@ -293,8 +313,7 @@ struct Schedule {
                 ++stage;
                 next = first_of(stage + 1, n_steps, n_stages);
             }
-            T = T0 - (double)stage * dT;
-            invT = 1.0 / T;
+            set();
         }
         return T;
     }
@@ -312,11 +331,22 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
 {
     const Words4 w = philox4x64(J.seed, J.chain_id, c0, c1, c2, 0);
     const int32_t p = J.support[__umul64hi(w.w0, (uint64_t)J.P)];
-    const double delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+    double delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
     const double fo = J.f[p];
     double fn = fo + delta;
-    if (fn < J.f_min) fn = J.f_min;
-    if (fn > J.f_max) fn = J.f_max;
+    if (J.proposal == PILA_PROP_REDRAW) {
+        // Eq. 3 as printed: the change is drawn again (counter word 3 = j)
+        // for the same pixel until the new value is in range; the draws are
+        // the same in every lane of the wavefront
+        for (uint64_t j = 1; (fn < J.f_min || fn > J.f_max) && j <= kRedrawMax; ++j) {
+            delta = J.delta_max * (2.0 * unit53(philox4x64(J.seed, J.chain_id, c0, c1, c2, j).w1) - 1.0);
+            fn = fo + delta;
+        }
+        if (fn < J.f_min || fn > J.f_max) fn = fo;
+    } else {
+        if (fn < J.f_min) fn = J.f_min;
+        if (fn > J.f_max) fn = J.f_max;
+    }
     const double d = fn - fo;
     const Real* len = (const Real*)J.len;
     const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
@@ -578,7 +608,7 @@ __device__ inline void write_stats(const ChainJob& J, const ChainState& cs)
         st.max_drift_r = cs.drift_r;
         st.max_drift_sse = cs.drift_sse;
         st.chain_launches = 0;
-        st.pad = 0;
+        st.body = 0;
         st.chain_kernel_ms = 0.0;
         *J.stats = st;
     }
@@ -674,7 +704,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
     // and the chain returns when a resync is due, which then runs grid-wide
     ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
     Schedule sched;
-    sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN);
+    sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
     const bool f32 = sizeof(Real) == 4;
 
     for (int64_t s = cs.s_begin; s < cs.n_steps; ++s) {
@@ -853,7 +883,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         lds_residual_load<Real>(J, r, rl);
     }
     Schedule sched;
-    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN);
+    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
 
     Draws cur, nxt;
     auto fill = [&](Draws& D, int64_t base) {
@@ -1153,7 +1183,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) lds_residual_load<Real>(J, r, rl);
     Schedule sched;
-    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN);
+    sched.start(s_begin, n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
 
     Draws cur, nxt;
     auto fill = [&](Draws& D, int64_t base) {

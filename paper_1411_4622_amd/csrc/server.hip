@@ -275,6 +275,7 @@ struct Request {
     PilaEntry* pila = nullptr;
     Block ws;
     bool live = false;
+    int32_t body = 0;  // PILA_BODY_* of the queue's kernel for this chain
 };
 
 uint64_t mix64(uint64_t h, uint64_t v)
@@ -670,7 +671,8 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     // long-row body for longer rows, else the general body
     const RingShape* ps = s->q[kPiped].shape;
     ChainJob probe = make_job(&e->geom, &e->csr, req->d_sino, &req->params, req->d_image, nullptr);
-    const bool f32 = req->params.precision == PILA_F32;
+    // redrawn proposals depend on the image value at the step: general body only
+    const bool f32 = req->params.precision == PILA_F32 && req->params.proposal == PILA_PROP_CLAMP;
     int qi = kGeneral;
     if (f32 && e->tcol && piped_allowed(&e->geom, &e->csr) && req->params.m_cand <= ps->waves * ps->cpw &&
         e->csr.max_row <= (kWave / ps->cpw) * ps->e && hybrid_lds(&probe, s->lds_bytes) <= s->lds_bytes)
@@ -708,6 +710,12 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     rq.pila = e;
     rq.ws = ws;
     rq.live = true;
+    if (qi == kGeneral) {
+        const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
+        rq.body = PILA_BODY_GENERAL | (rb <= s->lds_bytes ? 0 : PILA_BODY_GLOBAL_R);
+    } else {
+        rq.body = (qi == kPiped ? PILA_BODY_PIPED : PILA_BODY_LONG) | PILA_BODY_GLOBAL_R;
+    }
     q.next = l + 1;
     __atomic_store_n(&q.ctl->tail, l + 1, __ATOMIC_RELEASE);
     *ticket = (l << 2) | (uint64_t)qi;
@@ -726,7 +734,10 @@ extern "C" int32_t srv_poll(srv_t* s, uint64_t ticket, int32_t* done, sat_stats*
     PILA_TRY(progress(s));
     RingSlot& sl = q->slots[l & s->mask];
     if (__atomic_load_n(&sl.done, __ATOMIC_ACQUIRE) != l + 1) return PILA_OK;
-    if (stats) std::memcpy(stats, (const void*)&sl.stats, sizeof(sat_stats));
+    if (stats) {
+        std::memcpy(stats, (const void*)&sl.stats, sizeof(sat_stats));
+        stats->body = q->reqs[l & s->mask].body;
+    }
     release_request(s, q->reqs[l & s->mask]);
     ++s->reaped;
     *done = 1;

@@ -58,21 +58,29 @@ def test_bad_geometry_is_einval(P):
     lib = P.load()
     from paper_1411_4622_amd._binding import CCsr
     csr = CCsr()
-    assert lib.pila_build(None, C.byref(csr), None) == P._binding.PILA_EINVAL
+    assert lib.pila_build(None, C.byref(csr), None, 0, None) == P._binding.PILA_EINVAL
     assert "NULL" in P.last_error()
     for n, U, K in ((0, 4, 8), (8, 0, 8), (8, 4, 0)):
         g = P.Geometry(max(n, 1), np.zeros(max(U, 1)), max(K, 1))
         g.c.n, g.c.n_angles, g.c.n_bins = n, U, K
-        assert lib.pila_build(C.byref(g.c), C.byref(csr), None) == P._binding.PILA_EINVAL
+        assert lib.pila_build(C.byref(g.c), C.byref(csr), None, 0, None) == P._binding.PILA_EINVAL
     g = _geom(P, angles=np.array([0.0, np.nan, 10.0, 20.0]))
-    assert lib.pila_build(C.byref(g.c), C.byref(csr), None) == P._binding.PILA_EINVAL
+    assert lib.pila_build(C.byref(g.c), C.byref(csr), None, 0, None) == P._binding.PILA_EINVAL
     assert "not finite" in P.last_error()
     g = _geom(P)
     g.c.len_dtype = 7
-    assert lib.pila_build(C.byref(g.c), C.byref(csr), None) == P._binding.PILA_EINVAL
+    assert lib.pila_build(C.byref(g.c), C.byref(csr), None, 0, None) == P._binding.PILA_EINVAL
     g = _geom(P)
-    assert lib.pila_build(C.byref(g.c), C.byref(csr), None) == P._binding.PILA_EINVAL
+    assert lib.pila_build(C.byref(g.c), C.byref(csr), None, 0, None) == P._binding.PILA_EINVAL
     assert "allocated" in P.last_error()
+    # caller scratch: size query, then NULL or too small is refused before any device work
+    fake = 0x1000
+    nb = C.c_size_t(0)
+    assert lib.pila_build_scratch_size(C.byref(g.c), C.byref(nb)) == 0 and nb.value == 8 * 8 + 256
+    csr = CCsr(0, 0, 0, 0, -1, fake, None, None, None, fake, fake, None, None)
+    assert lib.pila_build(C.byref(g.c), C.byref(csr), None, nb.value, None) == P._binding.PILA_EINVAL
+    assert lib.pila_build(C.byref(g.c), C.byref(csr), fake, nb.value - 1, None) == P._binding.PILA_ENOMEM
+    assert "scratch" in P.last_error()
 
 
 def test_bad_sat_arguments(P):
@@ -95,6 +103,12 @@ def test_bad_sat_arguments(P):
         rc = lib.sat_run(C.byref(g.c), C.byref(csr), fake, C.byref(p), fake, fake, 1 << 30, None,
                          None, None)
         assert rc == P._binding.PILA_EINVAL, bad
+    for field, val in (("schedule", 3), ("schedule", -1), ("proposal", 2)):
+        p = P.SatParams(n_steps=10, T0=1e-2, TN=1e-6).c()
+        setattr(p, field, val)
+        rc = lib.sat_run(C.byref(g.c), C.byref(csr), fake, C.byref(p), fake, fake, 1 << 30, None,
+                         None, None)
+        assert rc == P._binding.PILA_EINVAL and field in P.last_error(), (field, val)
     # workspace too small
     p = P.SatParams(n_steps=10, T0=1e-2, TN=1e-6).c()
     rc = lib.sat_run(C.byref(g.c), C.byref(csr), fake, C.byref(p), fake, fake, 16, None, None, None)

@@ -41,13 +41,14 @@ def _gpu_chain(P, sl, dtype, params, trace=True):
     return out, st, tr
 
 
-def _oracle_chain(sl, params):
+def _oracle_chain(sl, params, **extra):
     csr = oracle.pila(sl.N, sl.U, sl.K, sl.angles, sl.mask)
     kw = dict(seed=params.seed, chain_id=params.chain_id, n_steps=params.n_steps,
               n_stages=params.n_stages, m_cand=params.m_cand, T0=params.T0, TN=params.TN,
               q_auto=params.q_auto, tn_ratio=params.tn_ratio, delta_max=params.delta_max,
               f_min=params.f_min, f_max=params.f_max, precision=params.precision,
               resync_every=params.resync_every)
+    kw.update(extra)
     return oracle.sat_run(sl.N, sl.U, sl.K, csr, sl.sino, sl.f0, mask=sl.mask, **kw)
 
 
