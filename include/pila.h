@@ -233,6 +233,27 @@ int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino
                 const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
                 sat_stats* h_stats, const sat_trace* trace, void* stream);
 
+/*
+ * sat_run_static - sat_run without a caller workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The chain's workspace
+ * is a static device array of PILA_STATIC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends; the call allocates
+ * nothing.  Same arguments, semantics and results as sat_run (the slot
+ * words go into the array when they fit after the chain state; the
+ * statistics carry no kernel timing: chain_kernel_ms = 0).  Every call on a
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other threads) race and give wrong results; each call writes
+ * every workspace byte it reads, so nothing has to be cleared between
+ * calls.  Errors: as sat_run, and ENOMEM when the chain state
+ * (sat_workspace_size without the slot words: the residual, per-64-ray
+ * sums, carry and stats, about U*K*(4 or 8) bytes) exceeds the array.
+ */
+#define PILA_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t sat_run_static(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                       const sat_params* params, double* d_image, sat_stats* h_stats,
+                       const sat_trace* trace, void* stream);
+
 /* One independent chain of a batch. */
 typedef struct sat_job {
     const pila_geom* geom;

@@ -25,7 +25,7 @@ PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
 BODY_PIPED, BODY_LONG, BODY_GENERAL = 1, 2, 3         # PILA_BODY_* kinds
 BODY_GLOBAL_R, BODY_SEGMENTED = 16, 32                # PILA_BODY_* flags
 
-EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run",
+EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run", "sat_run_static",
             "sat_batch_workspace_size", "sat_run_batch", "sirt_workspace_size", "sirt_run",
             "srv_create", "srv_prepare", "srv_submit", "srv_poll", "srv_cancel", "srv_get_status",
             "srv_destroy", "pila_get_device_info", "pila_last_error"]
@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.sat_workspace_size.argtypes = [G, C.POINTER(CSatParams), C.POINTER(C.c_size_t)]
     lib.sat_run.argtypes = [G, CS, V, C.POINTER(CSatParams), V, V, C.c_size_t,
                             C.POINTER(CSatStats), C.POINTER(CSatTrace), V]
+    lib.sat_run_static.argtypes = [G, CS, V, C.POINTER(CSatParams), V, C.POINTER(CSatStats),
+                                   C.POINTER(CSatTrace), V]
     lib.sat_batch_workspace_size.argtypes = [I32, C.POINTER(CSatJob), C.POINTER(C.c_size_t)]
     lib.sat_run_batch.argtypes = [I32, C.POINTER(CSatJob), C.POINTER(CSatLaunch), V, C.c_size_t,
                                   C.POINTER(CSatStats), V]
@@ -352,6 +354,30 @@ def sat_run(pila: Pila, sino, params: SatParams, image, workspace=None, trace: b
                           image.data_ptr(), ws.data_ptr(), ws.numel(),
                           C.byref(st) if st is not None else None,
                           C.byref(ctr) if ctr is not None else None, _stream()))
+    return (_stats_dict(st) if st is not None else None), tr
+
+
+def sat_run_static(pila: Pila, sino, params: SatParams, image, trace: bool = False,
+                   stats: bool = True):
+    """sat_run on the library's static device scratch (no allocation by the
+    library; the trace tensors, if asked for, are allocated here)."""
+    torch = _torch()
+    g = pila.geom
+    assert image.dtype == torch.float64 and image.is_cuda and image.is_contiguous()
+    assert sino.dtype == torch.float64 and sino.is_cuda and sino.is_contiguous()
+    p = params.c()
+    tr = None
+    ctr = None
+    if trace:
+        n = params.n_steps
+        tr = dict(m_star=torch.empty(n, dtype=torch.int32, device=image.device),
+                  accept=torch.empty(n, dtype=torch.uint8, device=image.device),
+                  dC=torch.empty(n, dtype=torch.float64, device=image.device))
+        ctr = CSatTrace(tr["m_star"].data_ptr(), tr["accept"].data_ptr(), tr["dC"].data_ptr())
+    st = CSatStats() if stats else None
+    _check(load().sat_run_static(C.byref(g.c), C.byref(pila.c), sino.data_ptr(), C.byref(p),
+                                 image.data_ptr(), C.byref(st) if st is not None else None,
+                                 C.byref(ctr) if ctr is not None else None, _stream()))
     return (_stats_dict(st) if st is not None else None), tr
 
 

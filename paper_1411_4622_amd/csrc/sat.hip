@@ -3,6 +3,7 @@
 // algorithm are in sat_chain.hpp.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "sat_chain.hpp"
@@ -542,11 +543,13 @@ extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* p
     return PILA_OK;
 }
 
-extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
-                           const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
-                           sat_stats* h_stats, const sat_trace* trace, void* stream)
+// One chain on the workspace d_ws (ws_bytes, at least chain_bytes; the
+// slot words go after the chain state when there is room).  timed: HIP
+// events around each chain-kernel launch (they are created per call).
+static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                            const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                            sat_stats* h_stats, const sat_trace* trace, void* stream, bool timed)
 {
-    clear_error();
     PILA_TRY(check_params(geom, csr, params));
     if (!d_sino || !d_image) return fail(PILA_EINVAL, "sinogram or image is NULL");
     const size_t need = chain_bytes(geom, params);
@@ -555,7 +558,7 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     hipStream_t st = (hipStream_t)stream;
     ChainJob J = make_job(geom, csr, d_sino, params, d_image, (char*)d_ws);
     LaunchTimer tm;
-    tm.on = h_stats != nullptr;
+    tm.on = h_stats != nullptr && timed;
     if (trace) {
         J.tr_m = trace->m_star;
         J.tr_acc = trace->accept;
@@ -580,9 +583,9 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
     const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
     // the pipelined body in global mode takes the entries' slot words
     // precomputed when the workspace has room for them
-    const size_t tcb = tcol_bytes(geom, params);
-    const bool tk = ps && !r_in_lds && table_lds <= budget && ps->k_glob_tk && tcb > 0 &&
-                    (size_t)csr->nnz * sizeof(int32_t) <= tcb && ws_bytes >= need + tcb;
+    const size_t tcb = align256((size_t)csr->nnz * sizeof(int32_t));
+    const bool tk = ps && !r_in_lds && table_lds <= budget && ps->k_glob_tk && tcol_bytes(geom, params) > 0 &&
+                    ws_bytes >= need + tcb;
     if (tk) {
         J.tcol = (const int32_t*)((char*)d_ws + need);
         if (csr->nnz > 0)
@@ -658,6 +661,65 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
         PILA_TRY(tm.total_ms(&h_stats->chain_kernel_ms));
     }
     return PILA_OK;
+}
+
+extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                           const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                           sat_stats* h_stats, const sat_trace* trace, void* stream)
+{
+    clear_error();
+    return sat_run_impl(geom, csr, d_sino, params, d_image, d_ws, ws_bytes, h_stats, trace, stream, true);
+}
+
+// ---------------------------------------------------------------------------
+// sat_run_static: sat_run on a workspace the library holds in a file-scope
+// device array, for callers that cannot allocate.  In host code the array's
+// name is only a stand-in for the symbol; its device address (one per GPU)
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[PILA_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_address(void** out)
+{
+    int dev = 0;
+    PILA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PILA_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        if (!ptr) return fail(PILA_EHIP, "hipGetSymbolAddress(scratch) gave a NULL address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PILA_OK;
+}
+}  // namespace
+
+extern "C" int32_t sat_run_static(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                                  const sat_params* params, double* d_image, sat_stats* h_stats,
+                                  const sat_trace* trace, void* stream)
+{
+    clear_error();
+    PILA_TRY(check_geom(geom));
+    if (!params) return fail(PILA_EINVAL, "params is NULL");
+    const size_t need = chain_bytes(geom, params);
+    if (need > PILA_STATIC_SCRATCH_BYTES)
+        return fail(PILA_ENOMEM,
+                    "the chain needs %zu bytes of workspace, above the %zu of the library's static scratch "
+                    "(use sat_run with a caller workspace)",
+                    need, (size_t)PILA_STATIC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    PILA_TRY(scratch_address(&ws));
+    return sat_run_impl(geom, csr, d_sino, params, d_image, ws, PILA_STATIC_SCRATCH_BYTES, h_stats, trace,
+                        stream, false);
 }
 
 // The PILAs of a batch whose FP32 chains may take the pipelined body (rows

@@ -116,6 +116,20 @@ def test_bad_sat_arguments(P):
     assert "workspace" in P.last_error()
 
 
+def test_static_entry_refuses_oversized_chain(P):
+    """sat_run_static checks the chain state against its static array before
+    any device work: a 3000 x 3000 ray FP64 residual (72 MB) is above 64 MiB."""
+    lib = P.load()
+    from paper_1411_4622_amd._binding import CCsr
+    g = P.Geometry(8, np.arange(3000) * 180.0 / 3000, 3000, None, "f64")
+    fake = 0x1000
+    csr = CCsr(10, 5, 4, 0, 3, fake, fake, fake, fake, fake, fake, fake, fake)
+    prm = P.SatParams(n_steps=10, T0=1e-2, TN=1e-6).c()
+    rc = lib.sat_run_static(C.byref(g.c), C.byref(csr), fake, C.byref(prm), fake, None, None, None)
+    assert rc == P._binding.PILA_ENOMEM
+    assert "static scratch" in P.last_error()
+
+
 def test_workspace_sizes(P):
     lib = P.load()
     from paper_1411_4622_amd._binding import CSirtParams
