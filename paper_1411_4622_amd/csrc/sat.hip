@@ -13,12 +13,19 @@ namespace pila {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// values of a chain's global residual: its tiled layout (tiles of 4 angles x
+// 8 bins) pads the angles to a multiple of 4 and the bins to a multiple of 8
+size_t residual_values(const pila_geom* g)
+{
+    return (size_t)((g->n_angles + 3) / 4) * 4 * (size_t)((g->n_bins + 7) / 8) * 8;
+}
+
 size_t chain_bytes(const pila_geom* g, const sat_params* p)
 {
     const size_t G = (size_t)g->n_angles * g->n_bins;
     const size_t T = (G + 63) / 64;
     const size_t rs = p->precision == PILA_F32 ? 4 : 8;
-    return align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)) +
+    return align256(rs * residual_values(g)) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)) +
            align256(sizeof(sat_stats));
 }
 
@@ -92,20 +99,26 @@ ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, con
     J.UL = 0;
     J.proposal = p->proposal;
     // g / K for g < 2^24 as (g * m) >> (24 + L), L = ceil(log2 K), m = ceil(2^(24+L) / K):
-    // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K
-    {
+    // the error g (m - 2^(24+L)/K) / 2^(24+L) stays below 2^-L <= 1/K; larger
+    // geometries divide (kdiv_s = 0)
+    J.kdiv_s = 0;
+    J.kdiv_m = 0;
+    if (G < ((size_t)1 << 24)) {
         uint32_t L = 0;
         while ((1u << L) < (uint32_t)J.K) ++L;
         const uint64_t den = (uint64_t)1 << (24 + L);
         J.kdiv_s = 24 + L;
         J.kdiv_m = (uint32_t)((den + (uint64_t)J.K - 1) / (uint64_t)J.K);
     }
+    J.rkb = (J.K + 7) / 8;
+    J.rpad = 0;
     const size_t T = (G + 63) / 64;
+    const size_t rb = align256(rs * residual_values(g));
     J.r = ws;
-    J.tsum = (double*)(ws + align256(rs * G));
-    J.tdrift = (double*)(ws + align256(rs * G) + align256(8 * T));
-    J.carry = (ChainCarry*)(ws + align256(rs * G) + 2 * align256(8 * T));
-    J.stats = (sat_stats*)(ws + align256(rs * G) + 2 * align256(8 * T) + align256(sizeof(ChainCarry)));
+    J.tsum = (double*)(ws + rb);
+    J.tdrift = (double*)(ws + rb + align256(8 * T));
+    J.carry = (ChainCarry*)(ws + rb + 2 * align256(8 * T));
+    J.stats = (sat_stats*)(ws + rb + 2 * align256(8 * T) + align256(sizeof(ChainCarry)));
     J.tr_m = nullptr;
     J.tr_acc = nullptr;
     J.tr_dc = nullptr;
@@ -246,7 +259,7 @@ __global__ __launch_bounds__(256) void sat_rebuild_kernel(ChainJob job, int meas
     const int G = job.U * job.K, T = (G + kWave - 1) / kWave;
     const int waves = gridDim.x * (blockDim.x >> 6);
     for (int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < T; t += waves)
-        rebuild_tile<Real>(job, (Real*)job.r, G, t, measure != 0, lane);
+        rebuild_tile<Real, true>(job, (Real*)job.r, G, t, measure != 0, lane);
 }
 
 // After the initial rebuild: sum of squares and Eq. 8, then the carry.
@@ -267,7 +280,7 @@ __global__ __launch_bounds__(512) void sat_setup_kernel(ChainJob job)
     double T0 = job.T0, TN = job.TN;
     int32_t status = PILA_OK;
     if (!(T0 > 0.0))
-        auto_temperature<Real>(job, (const Real*)job.r, sse, sh, lane, wave, NW, &T0, &TN, &status);
+        auto_temperature<Real, true>(job, (const Real*)job.r, sse, sh, lane, wave, NW, &T0, &TN, &status);
     if (threadIdx.x == 0) {
         ChainCarry& c = *job.carry;
         c.s_next = 0;
@@ -391,11 +404,9 @@ __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* 
     }
 }
 
-__global__ void zero_int_kernel(int* p)
+__global__ void zero_ints_kernel(int* p, int n)
 {
-    p[0] = 0;
-    p[1] = 0;
-    p[2] = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -680,8 +691,9 @@ extern "C" int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const dou
 // ---------------------------------------------------------------------------
 static __device__ __align__(256) char scratch[PILA_STATIC_SCRATCH_BYTES];
 
-namespace {
 constexpr int kMaxDevices = 64;
+
+namespace {
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices] = {};
 
@@ -722,6 +734,30 @@ extern "C" int32_t sat_run_static(const pila_geom* geom, const pila_csr* csr, co
                         stream, false);
 }
 
+// A batch runs its chains in groups, one persistent kernel per group: the
+// pipelined body at each register shape its chains need, the long-row body
+// and the general body.  The groups' kernels run side by side on forked
+// streams, so no chain waits for another group's kernel to end.
+constexpr int kMaxGroups = 8;
+constexpr int kMaxAux = kMaxGroups - 1;
+
+// Streams that the groups after the first run on, per device, created on
+// first use at the default priority and kept until the process ends.
+static int32_t aux_streams(int n, hipStream_t* out)
+{
+    static std::mutex mu;
+    static hipStream_t streams[kMaxDevices][kMaxAux] = {};
+    int dev = 0;
+    PILA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(PILA_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < n; ++i) {
+        if (!streams[dev][i]) PILA_HIP(hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking));
+        out[i] = streams[dev][i];
+    }
+    return PILA_OK;
+}
+
 // The PILAs of a batch whose FP32 chains may take the pipelined body (rows
 // of at most 512 entries): each gets one slot word per entry, shared by the
 // batch's chains on it (their LDS layouts are the same).
@@ -743,7 +779,7 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
     clear_error();
     if (n_jobs < 0 || (n_jobs > 0 && !jobs) || !bytes) return fail(PILA_EINVAL, "bad batch arguments");
     size_t total = align256(sizeof(ChainJob) * (size_t)(n_jobs > 0 ? n_jobs : 1)) +
-                   align256(sizeof(int) * (3 + (size_t)(n_jobs > 0 ? n_jobs : 1)));
+                   align256(sizeof(int) * (kMaxGroups + (size_t)(n_jobs > 0 ? n_jobs : 1)));
     for (int32_t j = 0; j < n_jobs; ++j) {
         PILA_TRY(check_geom(jobs[j].geom));
         total += chain_bytes(jobs[j].geom, &jobs[j].params);
@@ -752,6 +788,13 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
     *bytes = total;
     return PILA_OK;
 }
+
+struct BatchGroup {
+    int kind;                       // PILA_BODY_PIPED, _LONG or _GENERAL
+    const BatchShape* shape;        // the pipelined register shape (kind PIPED)
+    std::vector<int> ids;           // its chains, longest first
+    double longest = 0.0;           // estimated work of its longest chain
+};
 
 extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch,
                                  void* d_ws, size_t ws_bytes, sat_stats* h_stats, void* stream)
@@ -766,19 +809,15 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     char* ws = (char*)d_ws;
     ChainJob* d_jobs = (ChainJob*)ws;
     int* d_ticket = (int*)(ws + align256(sizeof(ChainJob) * (size_t)n_jobs));
-    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (3 + (size_t)n_jobs));
+    int* d_order = d_ticket + kMaxGroups;
+    char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (kMaxGroups + (size_t)n_jobs));
     std::vector<ChainJob> host((size_t)n_jobs);
-    int max_m = 1, max_row = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const sat_job& jb = jobs[j];
         PILA_TRY(check_params(jb.geom, jb.csr, &jb.params));
         if (!jb.d_sino || !jb.d_image) return fail(PILA_EINVAL, "job %d: sinogram or image is NULL", j);
         host[j] = make_job(jb.geom, jb.csr, jb.d_sino, &jb.params, jb.d_image, cur);
         cur += chain_bytes(jb.geom, &jb.params);
-        if (jb.params.precision == PILA_F32) {
-            max_m = jb.params.m_cand > max_m ? jb.params.m_cand : max_m;
-            max_row = jb.csr->max_row > max_row ? jb.csr->max_row : max_row;
-        }
     }
     int waves = 4, per_cu = 2, use_lds = 1;
     if (launch) {
@@ -789,20 +828,6 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
         return fail(PILA_EINVAL, "waves_per_chain must be 1, 2, 4, 8 or 16");
     if (per_cu < 1 || per_cu > 32) return fail(PILA_EINVAL, "chains_per_cu must be in 1..32");
-    // pipelined kernel shape: the fewest estimates per wavefront that cover
-    // every FP32 chain's M, then the smallest register row for the longest row
-    const BatchShape* bs = nullptr;
-    if (waves * kWave <= kPipedThreads) {
-        for (int cpw : {1, 2, 4}) {
-            if (max_m > waves * cpw) continue;
-            for (const BatchShape& sp : batch_shapes()) {
-                if (sp.cpw != cpw || max_row > (kWave / cpw) * sp.e) continue;
-                bs = &sp;
-                break;
-            }
-            if (bs) break;
-        }
-    }
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
     int lds = 0;
@@ -810,95 +835,130 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         const int per_wg = (int)(prop.sharedMemPerBlock / (size_t)per_cu) - (int)sizeof(ChainShared) - 512;
         lds = per_wg > 0 ? (per_wg & ~255) : 0;
     }
-    // split the chains: pipelined (FP32, fits the shape and the LDS table),
-    // long rows (FP32, one estimate per wavefront) and general
-    std::vector<int> piped_ids, long_ids, simple_ids;
-    for (int32_t j = 0; j < n_jobs; ++j) {
-        ChainJob& J = host[j];
-        const bool ahead = J.proposal == PILA_PROP_CLAMP;
-        bool ok = ahead && bs && J.precision == PILA_F32 && piped_allowed(jobs[j].geom, jobs[j].csr) &&
-                  J.max_row <= (kWave / bs->cpw) * bs->e && J.m_cand <= waves * bs->cpw;
-        if (ok) ok = hybrid_lds(&J, lds) <= lds;  // LDS part of the residual
-        if (ok) {
-            piped_ids.push_back(j);
-            continue;
-        }
-        if (ahead && J.precision == PILA_F32 && waves * kWave <= kPipedThreads && J.m_cand <= waves &&
-            long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
-            long_lds(&J, lds);
-            long_ids.push_back(j);
-            continue;
-        }
-        J.UL = 0;
-        simple_ids.push_back(j);
-    }
-    // longest chains first (estimated work: steps x estimates x mean row
-    // length), so that no long chain starts late behind short ones and sets
-    // the batch's makespan; results do not depend on the order
+    // estimated work of a chain: steps x estimates x mean row length
     auto work = [&](int j) {
         const double row = jobs[j].csr->n_support > 0
                                ? (double)jobs[j].csr->nnz / (double)jobs[j].csr->n_support
                                : 1.0;
         return (double)jobs[j].params.n_steps * (double)jobs[j].params.m_cand * (row + 8.0);
     };
-    for (std::vector<int>* ids : {&piped_ids, &long_ids, &simple_ids})
-        std::stable_sort(ids->begin(), ids->end(), [&](int a, int b) { return work(a) > work(b); });
-    // slot words of the pipelined chains' PILAs (the batch's pipelined kernel reads them)
+    // each chain's body: the pipelined body at the smallest register shape
+    // that holds its rows (the fewest estimates per wavefront first), else
+    // the long-row body, else the general body
+    std::vector<BatchGroup> groups;
+    auto group_of = [&](int kind, const BatchShape* shape) -> BatchGroup& {
+        for (BatchGroup& g : groups)
+            if (g.kind == kind && g.shape == shape) return g;
+        groups.push_back(BatchGroup{kind, shape, {}, 0.0});
+        return groups.back();
+    };
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        ChainJob& J = host[j];
+        const bool ahead = J.proposal == PILA_PROP_CLAMP;
+        const bool f32 = ahead && J.precision == PILA_F32 && waves * kWave <= kPipedThreads;
+        const BatchShape* bs = nullptr;
+        if (f32 && piped_allowed(jobs[j].geom, jobs[j].csr)) {
+            for (int cpw : {1, 2, 4}) {
+                if (J.m_cand > waves * cpw) continue;
+                for (const BatchShape& sp : batch_shapes())
+                    if (sp.cpw == cpw && J.max_row <= (kWave / cpw) * sp.e) {
+                        bs = &sp;
+                        break;
+                    }
+                if (bs) break;
+            }
+            if (bs && hybrid_lds(&J, lds) > lds) bs = nullptr;  // LDS part of the residual
+        }
+        int kind = PILA_BODY_GENERAL;
+        if (bs) {
+            kind = PILA_BODY_PIPED;
+        } else if (f32 && J.m_cand <= waves && long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
+            long_lds(&J, lds);
+            kind = PILA_BODY_LONG;
+        } else {
+            J.UL = 0;
+        }
+        BatchGroup& g = group_of(kind, bs);
+        g.ids.push_back(j);
+        g.longest = std::max(g.longest, work(j));
+    }
+    if ((int)groups.size() > kMaxGroups) return fail(PILA_EINVAL, "too many chain groups");
+    // longest chains first within a group, so that no long chain starts late
+    // behind short ones and sets the makespan (results do not depend on the
+    // order); the group holding the batch's longest chain launches first
+    for (BatchGroup& g : groups)
+        std::stable_sort(g.ids.begin(), g.ids.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::stable_sort(groups.begin(), groups.end(),
+                     [](const BatchGroup& a, const BatchGroup& b) { return a.longest > b.longest; });
+    // slot words of the pipelined chains' PILAs (the pipelined kernels read them)
     {
         const std::vector<const pila_csr*> tp = batch_tcol_pilas(n_jobs, jobs);
         std::vector<int32_t*> where(tp.size(), nullptr);
-        for (int j : piped_ids) {
-            size_t i = 0;
-            while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
-            if (i == tp.size()) return fail(PILA_EINVAL, "job %d: no slot-word room for its PILA", j);
-            if (!where[i]) {
-                where[i] = (int32_t*)cur;
-                cur += align256(sizeof(int32_t) * (size_t)tp[i]->nnz);
-                tcol_kernel<<<(unsigned)std::min<int64_t>((tp[i]->nnz + 255) / 256, 8192), 256, 0, st>>>(
-                    host[j], tp[i]->nnz, where[i]);
+        for (const BatchGroup& g : groups) {
+            if (g.kind != PILA_BODY_PIPED) continue;
+            for (int j : g.ids) {
+                size_t i = 0;
+                while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
+                if (i == tp.size()) return fail(PILA_EINVAL, "job %d: no slot-word room for its PILA", j);
+                if (!where[i]) {
+                    where[i] = (int32_t*)cur;
+                    cur += align256(sizeof(int32_t) * (size_t)tp[i]->nnz);
+                    PILA_TRY(launch_tcol(host[j], tp[i]->nnz, where[i], st));
+                }
+                host[j].tcol = where[i];
             }
-            host[j].tcol = where[i];
         }
     }
-    std::vector<int> order(piped_ids);
-    order.insert(order.end(), long_ids.begin(), long_ids.end());
-    order.insert(order.end(), simple_ids.begin(), simple_ids.end());
-    // [0]: pipelined ticket, [1]: general ticket, [2]: long-row ticket, then the order
-    int* d_order = d_ticket + 3;
+    std::vector<int> order;
+    for (const BatchGroup& g : groups) order.insert(order.end(), g.ids.begin(), g.ids.end());
     PILA_HIP(hipMemcpyAsync(d_jobs, host.data(), sizeof(ChainJob) * host.size(), hipMemcpyHostToDevice, st));
     PILA_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
-    zero_int_kernel<<<1, 1, 0, st>>>(d_ticket);
+    zero_ints_kernel<<<1, 64, 0, st>>>(d_ticket, kMaxGroups);
+    PILA_HIP(hipGetLastError());
+    // fork: every group after the first waits for the uploads on its own stream
+    const int n_aux = (int)groups.size() - 1;
+    hipStream_t aux[kMaxAux] = {};
+    hipEvent_t fork = nullptr, join[kMaxAux] = {};
+    struct Events {
+        hipEvent_t* f;
+        hipEvent_t* j;
+        int n;
+        ~Events()
+        {
+            if (*f) (void)hipEventDestroy(*f);
+            for (int i = 0; i < n; ++i)
+                if (j[i]) (void)hipEventDestroy(j[i]);
+        }
+    } cleanup{&fork, join, n_aux};
+    if (n_aux > 0) {
+        PILA_TRY(aux_streams(n_aux, aux));
+        PILA_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        PILA_HIP(hipEventRecord(fork, st));
+        for (int i = 0; i < n_aux; ++i) {
+            PILA_HIP(hipStreamWaitEvent(aux[i], fork, 0));
+            PILA_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+        }
+    }
     const ChainJob* jobs_arg = d_jobs;
     int lds_arg = lds;
-    if (!piped_ids.empty()) {
-        int n_arg = (int)piped_ids.size();
-        const int* order_arg = d_order;
-        int* ticket_arg = d_ticket;
+    size_t first = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const BatchGroup& g = groups[gi];
+        hipStream_t gs = gi == 0 ? st : aux[gi - 1];
+        int n_arg = (int)g.ids.size();
+        const int* order_arg = d_order + first;
+        int* ticket_arg = d_ticket + gi;
+        first += g.ids.size();
         void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
         const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
-        PILA_TRY(set_lds((const void*)bs->k, lds));
-        PILA_HIP(hipLaunchKernel((const void*)bs->k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
-    }
-    if (!long_ids.empty()) {
-        int n_arg = (int)long_ids.size();
-        const int* order_arg = d_order + piped_ids.size();
-        int* ticket_arg = d_ticket + 2;
-        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
-        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
-        const void* k = (const void*)sat_batch_long_kernel<kLongE>;
+        const void* k = g.kind == PILA_BODY_PIPED ? (const void*)g.shape->k
+                        : g.kind == PILA_BODY_LONG ? (const void*)sat_batch_long_kernel<kLongE>
+                                                   : (const void*)sat_batch_simple_kernel;
         PILA_TRY(set_lds(k, lds));
-        PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, st));
+        PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, gs));
+        if (gi > 0) PILA_HIP(hipEventRecord(join[gi - 1], gs));
     }
-    if (!simple_ids.empty()) {
-        int n_arg = (int)simple_ids.size();
-        const int* order_arg = d_order + piped_ids.size() + long_ids.size();
-        int* ticket_arg = d_ticket + 1;
-        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
-        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
-        PILA_TRY(set_lds((const void*)sat_batch_simple_kernel, lds));
-        PILA_HIP(hipLaunchKernel((const void*)sat_batch_simple_kernel, dim3(grid), dim3(waves * kWave), args,
-                                 (size_t)lds, st));
-    }
+    for (int i = 0; i < n_aux; ++i) PILA_HIP(hipStreamWaitEvent(st, join[i], 0));
     PILA_HIP(hipGetLastError());
     if (h_stats) {
         for (int32_t j = 0; j < n_jobs; ++j)
@@ -907,13 +967,13 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     // the descriptor upload reads host memory owned by this call
     PILA_HIP(hipStreamSynchronize(st));
     if (h_stats) {
-        for (int j : piped_ids) h_stats[j].body = PILA_BODY_PIPED | PILA_BODY_GLOBAL_R;
-        for (int j : long_ids) h_stats[j].body = PILA_BODY_LONG | PILA_BODY_GLOBAL_R;
-        for (int j : simple_ids) {
-            const ChainJob& J = host[j];
-            const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
-            h_stats[j].body = PILA_BODY_GENERAL | (rb <= lds ? 0 : PILA_BODY_GLOBAL_R);
-        }
+        for (const BatchGroup& g : groups)
+            for (int j : g.ids) {
+                const ChainJob& J = host[j];
+                const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
+                const bool glob = g.kind != PILA_BODY_GENERAL || rb > lds;
+                h_stats[j].body = g.kind | (glob ? PILA_BODY_GLOBAL_R : 0);
+            }
     }
     return PILA_OK;
 }

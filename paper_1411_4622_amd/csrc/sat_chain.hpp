@@ -56,7 +56,8 @@ struct ChainJob {
     int32_t max_row, schedule;   // schedule: PILA_SCHED_* cooling law
     int32_t k_lo, Kc, UL, proposal;  // LDS part of the residual: angles u < UL, bins k_lo ..
                                      // k_lo+Kc-1; proposal: PILA_PROP_* (clamp or redraw)
-    uint32_t kdiv_m, kdiv_s;     // g / K = (g * kdiv_m) >> kdiv_s for g < 2^24
+    uint32_t kdiv_m, kdiv_s;     // g / K = (g * kdiv_m) >> kdiv_s for g < 2^24 (kdiv_s = 0: divide)
+    int32_t rkb, rpad;           // global residual layout: 8-bin blocks per angle group (rpos)
     int64_t n_steps, resync_every;
     uint64_t seed, chain_id;
     double T0, TN, tn_ratio, delta_max, f_min, f_max, ln09;
@@ -125,7 +126,7 @@ __device__ __forceinline__ T lane0(T x)
 
 // uniform_job below copies every field by name: a field added to ChainJob
 // must be added there too (this size check is the reminder)
-static_assert(sizeof(ChainJob) == 312, "ChainJob changed: update uniform_job");
+static_assert(sizeof(ChainJob) == 320, "ChainJob changed: update uniform_job");
 
 __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
 {
@@ -133,7 +134,7 @@ __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
 #define PILA_F(f) J.f = lane0(d.f);
     PILA_F(N) PILA_F(U) PILA_F(K) PILA_F(P) PILA_F(precision) PILA_F(m_cand) PILA_F(n_stages)
     PILA_F(q_auto) PILA_F(max_row) PILA_F(schedule) PILA_F(k_lo) PILA_F(Kc) PILA_F(UL) PILA_F(proposal)
-    PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
+    PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(rkb) PILA_F(rpad) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
     PILA_F(T0) PILA_F(TN) PILA_F(tn_ratio) PILA_F(delta_max) PILA_F(f_min) PILA_F(f_max) PILA_F(ln09)
     PILA_F(row_ptr) PILA_F(col) PILA_F(len) PILA_F(t_row_ptr) PILA_F(t_col) PILA_F(t_len)
     PILA_F(support) PILA_F(sino) PILA_F(f) PILA_F(r) PILA_F(tsum) PILA_F(tdrift) PILA_F(carry)
@@ -269,6 +270,36 @@ __device__ __forceinline__ double uniform_f64(double v)
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
+// Layout of a residual held in global memory: tiles of 4 angles x 8 bins
+// (32 values: one 128-byte line in FP32), tile (u / 4, k / 8) at
+// ((u / 4) rkb + k / 8) 32, value (u mod 4) 8 + k mod 8 inside it, with
+// rkb = ceil(K / 8).  A pixel's ray moves by about (distance from the axis)
+// x pi / U bins from one angle to the next, so consecutive entries of a
+// PILA row (ascending angle) often share a tile and its cache line, where
+// the row-major sinogram would give each entry a line of its own.  A
+// residual held in LDS stays row-major (index g = u K + k).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t rpos(const ChainJob& J, int u, int k)
+{
+    return ((uint32_t)((u >> 2) * J.rkb + (k >> 3)) << 5) | ((uint32_t)(u & 3) << 3) | (uint32_t)(k & 7);
+}
+__device__ __forceinline__ int angle_of(const ChainJob& J, int32_t g)
+{
+    return J.kdiv_s ? (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s) : (int)((uint32_t)g / (uint32_t)J.K);
+}
+__device__ __forceinline__ uint32_t rpos_g(const ChainJob& J, int32_t g)
+{
+    const int u = angle_of(J, g);
+    return rpos(J, u, g - u * J.K);
+}
+// index of ray g in a residual array: tiled in global memory, row-major in LDS
+template <bool GLOB>
+__device__ __forceinline__ uint32_t ridx(const ChainJob& J, int32_t g)
+{
+    return GLOB ? rpos_g(J, g) : (uint32_t)g;
+}
+
+// ---------------------------------------------------------------------------
 // cooling schedule: stage n = floor(s n_stages / n_steps), tracked
 // incrementally without a 64-bit division per step; with N = n_stages,
 //   Eq. 2 (linear):                        T_n = T0 - n (T0 - TN) / N
@@ -325,7 +356,7 @@ struct Schedule {
 
 // Draw one estimate (Step 2, Eq. 3 with a clamp to [f_min, f_max]) and return
 // its row sum (whole wavefront, canonical order) in every lane.
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint64_t c0, uint64_t c1,
                              uint64_t c2, int lane, int32_t* p_out, double* fn_out, double* d_out)
 {
@@ -366,7 +397,7 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
         }
         Real rr[U];
 #pragma unroll
-        for (int c = 0; c < U; ++c) rr[c] = r[cc[c]];
+        for (int c = 0; c < U; ++c) rr[c] = r[ridx<GLOB>(J, cc[c])];
 #pragma unroll
         for (int c = 0; c < U; ++c) {
             if (q0 + (int64_t)c * kWave < e) {
@@ -390,7 +421,7 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
 // butterfly over the quarter adds the 16 partials.  Lane j then holds ray
 // t*64 + j.  In-group and grid-wide rebuilds both run this function, so they
 // give the same bits.
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int t, bool measure,
                              int lane)
 {
@@ -431,8 +462,9 @@ __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int
     double sq = 0.0, dr = 0.0;
     if (g < G) {
         const double r64 = acc - J.sino[g];
-        if (measure) dr = fabs((double)r[g] - r64);
-        r[g] = (Real)r64;
+        const uint32_t at = ridx<GLOB>(J, g);
+        if (measure) dr = fabs((double)r[at] - r64);
+        r[at] = (Real)r64;
         sq = r64 * r64;
     }
     sq = wave_canon_sum(sq);
@@ -459,14 +491,14 @@ __device__ inline void tile_totals(const ChainJob& J, int G, bool measure, int l
 }
 
 // in-workgroup rebuild of the whole residual; returns (sse, drift) to all
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ void rebuild_in_group(const ChainJob& J, Real* r, ChainShared& sh, bool measure, int lane,
                                  int wave, int NW, double* sse, double* drift)
 {
     const int G = J.U * J.K;
     const int T = (G + kWave - 1) / kWave;
     __syncthreads();
-    for (int t = wave; t < T; t += NW) rebuild_tile<Real>(J, r, G, t, measure, lane);
+    for (int t = wave; t < T; t += NW) rebuild_tile<Real, GLOB>(J, r, G, t, measure, lane);
     __syncthreads();
     if (wave == 0) {
         double s, d;
@@ -490,7 +522,7 @@ struct ChainState {
 
 // Eq. 8: T0 from q_auto uphill single-pixel estimates of the starting image
 // (Philox counter (q, 0, 2, 0)), summed in q order.
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, ChainShared& sh, int lane,
                                  int wave, int NW, double* T0, double* TN, int32_t* status)
 {
@@ -503,7 +535,7 @@ __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, C
         if (q < limit) {
             int32_t p;
             double fn, d;
-            const double S = (double)estimate_sum<Real>(J, r, (uint64_t)q, 0, 2, lane, &p, &fn, &d);
+            const double S = (double)estimate_sum<Real, GLOB>(J, r, (uint64_t)q, 0, 2, lane, &p, &fn, &d);
             const double cn = sqrt(fmax(sse + S, 0.0) / KU), co = sqrt(sse / KU);
             const double den = cn + co;
             if (lane == 0) sh.S[wave] = den == 0.0 ? 0.0 : (S / KU) / den;
@@ -536,16 +568,16 @@ __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, C
 }
 
 // Step 1 and Eq. 8 inside the workgroup.
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ ChainState chain_setup(const ChainJob& J, Real* r, ChainShared& sh, int lane, int wave, int NW)
 {
     ChainState cs;
     double drift;
-    rebuild_in_group<Real>(J, r, sh, false, lane, wave, NW, &cs.sse, &drift);
+    rebuild_in_group<Real, GLOB>(J, r, sh, false, lane, wave, NW, &cs.sse, &drift);
     cs.T0 = J.T0;
     cs.TN = J.TN;
     cs.status = PILA_OK;
-    if (!(cs.T0 > 0.0)) auto_temperature<Real>(J, r, cs.sse, sh, lane, wave, NW, &cs.T0, &cs.TN, &cs.status);
+    if (!(cs.T0 > 0.0)) auto_temperature<Real, GLOB>(J, r, cs.sse, sh, lane, wave, NW, &cs.T0, &cs.TN, &cs.status);
     cs.n_steps = cs.status == PILA_OK ? J.n_steps : 0;
     cs.accepts = cs.accepts_nz = cs.since = cs.s_begin = 0;
     cs.resyncs = 0;
@@ -676,12 +708,12 @@ __device__ __forceinline__ void count_decision(const ChainJob& J, ChainState& cs
     }
 }
 
-template <typename Real>
+template <typename Real, bool GLOB>
 __device__ __forceinline__ void resync_in_group(const ChainJob& J, ChainState& cs, Real* r, ChainShared& sh,
                                                 int lane, int wave, int NW)
 {
     double sse64, drift;
-    rebuild_in_group<Real>(J, r, sh, true, lane, wave, NW, &sse64, &drift);
+    rebuild_in_group<Real, GLOB>(J, r, sh, true, lane, wave, NW, &sse64, &drift);
     cs.drift_r = fmax(cs.drift_r, drift);
     const double ds = sse64 > 0.0 ? fabs(cs.sse - sse64) / sse64 : fabs(cs.sse - sse64);
     cs.drift_sse = fmax(cs.drift_sse, ds);
@@ -702,7 +734,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
     Real* r = LDS ? (Real*)lds : (Real*)J.r;
     // segmented (global residual only): the chain state comes from the carry
     // and the chain returns when a resync is due, which then runs grid-wide
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !LDS>(J, r, sh, lane, wave, NW);
     Schedule sched;
     sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
     const bool f32 = sizeof(Real) == 4;
@@ -712,7 +744,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
         for (int m = wave; m < M; m += NW) {
             int32_t p;
             double fn, d;
-            const Real S = estimate_sum<Real>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
+            const Real S = estimate_sum<Real, !LDS>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
             if (lane == 0) {
                 sh.S[m] = (double)S;
                 sh.p[m] = p;
@@ -744,11 +776,14 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
                     cc[c] = J.col[q];
                     ll[c] = len[q];
                 }
+                uint32_t at[U];
 #pragma unroll
-                for (int c = 0; c < U; ++c) rr[c] = r[cc[c]];
+                for (int c = 0; c < U; ++c) at[c] = ridx<!LDS>(J, cc[c]);
+#pragma unroll
+                for (int c = 0; c < U; ++c) rr[c] = r[at[c]];
 #pragma unroll
                 for (int c = 0; c < U; ++c)
-                    if (q0 + (int64_t)c * kWave < e) r[cc[c]] = rr[c] + dr * ll[c];
+                    if (q0 + (int64_t)c * kWave < e) r[at[c]] = rr[c] + dr * ll[c];
             }
             if (lane == 0) J.f[p] = sh.fn[dn.ms];
         }
@@ -759,7 +794,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
                 save_carry(J, cs, s + 1, true);
                 return;
             }
-            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !LDS>(J, cs, r, sh, lane, wave, NW);
         }
         __syncthreads();
         if (cancel_seen(J, sh, s)) {
@@ -836,7 +871,7 @@ __device__ void lds_residual_load(const ChainJob& J, const Real* r, Real* rl)
     const int n = J.UL * J.Kc;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int u = i / J.Kc, k = J.k_lo + i % J.Kc;
-        rl[i] = r[u * J.K + k];
+        rl[i] = r[rpos(J, u, k)];
     }
 }
 template <typename Real>
@@ -845,7 +880,7 @@ __device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
     const int n = J.UL * J.Kc;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int u = i / J.Kc, k = J.k_lo + i % J.Kc;
-        r[u * J.K + k] = rl[i];
+        r[rpos(J, u, k)] = rl[i];
     }
 }
 
@@ -875,7 +910,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     Real* rl = (Real*)(lds + ((16 * (size_t)J.U + 2 * sizeof(Real) * (size_t)J.U + 15) & ~(size_t)15));
     const Real* lenp = (const Real*)J.len;
 
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS>(J, r, sh, lane, wave, NW);
     const int64_t n_steps = cs.n_steps;
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) {
@@ -967,13 +1002,16 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 #pragma unroll
         for (int e = 0; e < E; ++e) S.tk[e] = ray_slot(J, S.col[e]);
     };
-    // ray index of entry e (outside the LDS part)
-    auto gcol = [&](const RowSet<Real, E>& S, int e) -> int32_t {
-        return kTK ? (S.tk[e] >> 14) * J.K + (S.tk[e] & 8191) : S.col[e];
+    // position of entry e's ray in the residual: in LDS (RLDS) its index; in
+    // the global residual (outside the LDS part) its tile position, from the
+    // angle and bin of its slot word or from the ray index
+    auto gcol = [&](const RowSet<Real, E>& S, int e) -> uint32_t {
+        if (RLDS) return (uint32_t)S.col[e];
+        return kTK ? rpos(J, S.tk[e] >> 14, S.tk[e] & 8191) : rpos_g(J, S.col[e]);
     };
     auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
-    // residual value of ray g outside the LDS part
-    auto rget = [&](int32_t g) -> Real { return RLDS ? r[g] : ld32((const Real*)r, (uint32_t)g); };
+    // residual value at a position of the global residual, or of ray g in LDS
+    auto rget = [&](uint32_t g) -> Real { return RLDS ? r[g] : ld32((const Real*)r, g); };
 
     RowSet<Real, E> A, B, C;
     prefetch(A, s_begin);
@@ -1055,7 +1093,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                     } else if (X.tk[e] & kLdsFlag) {
                         rl[X.tk[e] & ~kLdsFlag] = rn;
                     } else {
-                        st32(r, (uint32_t)gcol(X, e), rn);
+                        st32(r, gcol(X, e), rn);
                         pkey[X.tk[e] >> 13] = ((int64_t)s << 13) | (X.tk[e] & 8191);
                         pval[X.tk[e] >> 13] = rn;
                     }
@@ -1078,7 +1116,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 save_carry(J, cs, s + 1, true);
                 return true;
             }
-            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !RLDS>(J, cs, r, sh, lane, wave, NW);
             co = sqrt(cs.sse / KU);
             if (!RLDS) lds_residual_load<Real>(J, r, rl);
             // the next two sets are drawn again after the rebuild, so that no
@@ -1108,7 +1146,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             if (in_lds(Y.tk[e]))
                 Y.rv[e] = rl[Y.tk[e] & ~kLdsFlag];
             else if (RLDS)
-                Y.rv[e] = rget(Y.col[e]);
+                Y.rv[e] = rget((uint32_t)Y.col[e]);
         }
         if (SERVED && cancel_seen(J, sh, s)) {
             cs.status = PILA_ECANCELED;
@@ -1178,7 +1216,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
     Real* rl = (Real*)lds;
     const Real* lenp = (const Real*)J.len;
 
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS>(J, r, sh, lane, wave, NW);
     const int64_t n_steps = cs.n_steps;
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) lds_residual_load<Real>(J, r, rl);
@@ -1248,19 +1286,21 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
             S.len[e] = ld32(lenp, at);
         }
     };
-    // residual value of ray g: LDS part (angles u < UL) or global memory
+    // residual value of ray g: LDS part (angles u < UL: *lidx its index) or
+    // global memory (*lidx = -1 - its position in the tiled layout)
     auto rget = [&](int32_t g, int* lidx) -> Real {
         if (RLDS) {
             *lidx = g;
             return r[g];
         }
-        const int u = (int)(((uint64_t)(uint32_t)g * J.kdiv_m) >> J.kdiv_s);
+        const int u = angle_of(J, g);
         if (u < J.UL) {
             *lidx = u * J.Kc + (g - u * J.K - J.k_lo);
             return rl[*lidx];
         }
-        *lidx = -1;
-        return ld32((const Real*)r, (uint32_t)g);
+        const uint32_t at = rpos(J, u, g - u * J.K);
+        *lidx = -1 - (int)at;
+        return ld32((const Real*)r, at);
     };
 
     LongRow<Real, E> A, B;
@@ -1317,7 +1357,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
                     else if (li[e] >= 0)
                         rl[li[e]] = rn;
                     else
-                        st32(r, (uint32_t)X.col[e], rn);
+                        st32(r, (uint32_t)(-1 - li[e]), rn);
                 }
             }
             // the entries beyond the registers: their rays differ from the
@@ -1331,7 +1371,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
                 else if (lo >= 0)
                     rl[lo] = rn;
                 else
-                    st32(r, (uint32_t)g, rn);
+                    st32(r, (uint32_t)(-1 - lo), rn);
             }
             if (lane == 0) J.f[X.p] = fn;
         }
@@ -1345,7 +1385,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
                 save_carry(J, cs, s + 1, true);
                 return true;
             }
-            resync_in_group<Real>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !RLDS>(J, cs, r, sh, lane, wave, NW);
             if (!RLDS) lds_residual_load<Real>(J, r, rl);
         }
         __syncthreads();
