@@ -1,28 +1,39 @@
 #!/usr/bin/env python3
 """Throughput of simulated annealing tomography with a PILA on one MI355X.
 
-Workload: one annealing chain on a 256 x 256 slice (10 random ellipses),
-180 angles in [0, 180), 367 unit bins, photon noise at I0 = 1e4 per ray,
-circular support, best of M = 16 estimates per step, 5e6 steps, FP32
-residual rebuilt in FP64 every 4096 accepted nonzero changes, T0 from
-Eq. 8 (Q = 200) and T_N = T0 / 1e3 under linear cooling over 1000 stages.
+Workload (default): a batch of 512 independent slices cut from one seeded
+3-D volume of 32 random ellipsoids, each slice N x N with N drawn from
+{128, 256, 512} and U angles from {90, 180, 360} in [0, 180), K =
+ceil(sqrt(2) N) unit bins, photon noise at I0 = 1e4 per ray, circular
+support; one annealing chain per slice: best of M = 8 estimates per step,
+16 sweeps of the support (steps = 16 x support pixels), FP32 residual
+rebuilt in FP64 every max(4096, nnz / 1024) accepted nonzero changes, T0
+from Eq. 8 (Q = 200), T_N = T0 / 1e3, linear cooling over 1000 stages.
 
-One benchmark step is one pass of the whole path over that slice: PILA
-build (pixel-major and ray-major), starting image, residual and Eq. 8, the
-5e6-step chain with its resyncs.  Inputs are in device memory before the
-timed region.  Reported value: SA estimates (proposals) evaluated per
-second over the timed steps.  Beside it: steps/s, slices/s, per-slice
-latency, final RMSE of the FP32 chain and of an FP64 chain with the same
-seeds, the roofline of the chain kernel, and the CPU oracle timed on a
-bounded sample of the same chain.
+One benchmark step is one pass of the whole path over that batch: the nine
+PILAs (pixel-major and ray-major), the starting images, and the batched
+chains (residuals, Eq. 8, the chains and their resyncs).  Inputs are in
+device memory before the timed region.  Reported value: SA estimates
+(proposals) evaluated per second over the timed steps.  Beside it: steps/s,
+slices/s, per-slice latency inside a batch (p50/p99), final RMSE and NRMSE
+of every slice and its ratio to an FP64 batch with the same seeds, the
+batch against the same chains run one at a time (sat_run), the roofline of
+the kernel that runs longest, the CPU oracle on a bounded sample of the same
+chains, and the noise-free 64 x 64 quality check of section III-B.
+
+Other workloads: --workload c2 (one chain, 256^2 x 180, M = 16), c3r (the
+batch with repeated phantoms), c4 (1024^2 x 720: SAT M = 32 and SIRT), c5
+(serving stream).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -38,26 +49,26 @@ def log(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def chain_kernel_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
-    """Algorithmic bytes of the chain kernel over a whole chain (FP32 PILA and residual).
+def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
+    """Algorithmic bytes of one FP32 chain in a batch.
 
     per estimate: support index 4, image value 8, row offsets 16, and per row
-    entry ray index 4 + length 4 + residual 4; per accepted estimate: per row
-    entry ray index 4 + length 4 + residual read 4 + write 4, image write 8.
-    The FP64 rebuilds at the resyncs (per PILA entry pixel index 4 + length 4
-    + image value 8, per ray 32) run in their own kernel and are not counted.
+    entry slot word 4 + length 4 + residual 4; per accepted estimate: per row
+    entry slot word 4 + length 4 + residual read 4 + write 4, image write 8.
+    In-group FP64 resyncs (per PILA entry pixel 4 + length 4 + image 8) are
+    not counted.
     """
     return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
 
 
-# HBM bytes per chain-kernel launch from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# runs of this benchmark, each scaled by the factor that makes the counter
-# read the known size of a plain device copy in the same run; valid only for
-# the kernel sources they were taken with (hash over the files below)
+# HBM bytes per dispatch of the kernel the roofline reports, from two
+# rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB
+# per dispatch), each scaled by the factor that makes the counter read the
+# known size of a plain device copy in the same run; valid only for the
+# kernel sources they were taken with (hash over the files below)
 TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
                    "paper_1411_4622_amd/csrc/common.hpp")
-TRAFFIC = {"sources_sha256": "cec2281accac605fc0998dce270a3680c42776dae036492060191677cfa4a570",
-           "bytes_per_launch": 143386283.5}
+TRAFFIC = {}
 
 
 def sources_hash() -> str:
@@ -67,25 +78,6 @@ def sources_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
-
-
-def cpu_baseline(sl, cfg, n_steps_cpu: int) -> dict:
-    import oracle
-    log("cpu baseline: oracle PILA for %dx%d, %d angles" % (sl.N, sl.N, sl.U))
-    csr = oracle.pila(sl.N, sl.U, sl.K, sl.angles, sl.mask)
-    kw = dict(seed=cfg["chain_seed"], chain_id=0, n_steps=n_steps_cpu, n_stages=cfg["n_stages"],
-              m_cand=cfg["M"], T0=None, q_auto=cfg["q_auto"], tn_ratio=cfg["tn_ratio"],
-              delta_max=cfg["delta_max"], f_min=cfg["f_min"], f_max=cfg["f_max"],
-              precision=cfg["precision"], resync_every=cfg["resync_every"])
-    log("cpu baseline: oracle chain, %d steps" % n_steps_cpu)
-    t0 = time.perf_counter()
-    oracle.sat_run(sl.N, sl.U, sl.K, csr, sl.sino, sl.f0, mask=sl.mask, trace=False, **kw)
-    dt = time.perf_counter() - t0
-    return {"value": n_steps_cpu * cfg["M"] / dt, "unit": "proposals/s", "cores": 1, "kind": "oracle",
-            "sample": "the same chain (same slice, M, FP32 residual with FP64 resync) cut to its "
-                      "first %d of %d steps, single thread, %.1f s; PILA build not timed"
-                      % (n_steps_cpu, cfg["n_steps"], dt),
-            "cpu": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def _cpu_model() -> str:
@@ -98,25 +90,376 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+def _pool(procs):
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    return ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn"))
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the host cores, one process per chain
+# ---------------------------------------------------------------------------
+
+def _cpu_pila(arg):
+    """Build one geometry's oracle PILA and save it (worker process)."""
+    import datagen
+    import oracle
+    N, U, K, where = arg
+    rp, col, ln = oracle.pila(N, U, K, datagen.angles_deg(U), datagen.circle_mask(N))
+    np.save(where + "_rp.npy", rp)
+    np.save(where + "_col.npy", col)
+    np.save(where + "_len.npy", ln)
+    return where
+
+
+def _cpu_chain(arg):
+    """One oracle chain, cut to its first steps (worker process)."""
+    import datagen
+    import oracle
+    where, N, U, K, sino, f0, kw = arg
+    csr = tuple(np.load(where + s, mmap_mode="r") for s in ("_rp.npy", "_col.npy", "_len.npy"))
+    csr = tuple(np.ascontiguousarray(a) for a in csr)
+    t0 = time.perf_counter()
+    oracle.sat_run(N, U, K, csr, sino, f0, mask=datagen.circle_mask(N), trace=False, **kw)
+    return time.perf_counter() - t0
+
+
+class CpuBaseline:
+    """The oracle (FP32 residual with FP64 resync, as the GPU chains) on a
+    bounded sample of the batch's chains: those of the 128^2 and 256^2 slices
+    (the oracle's ray-traced PILA of a 512^2 slice takes a minute to build),
+    taken in turn from each geometry until there are two per host core, each
+    cut to its first steps so that it does about 1.5e8 row entries of work.
+    The PILAs are built first in a pool of their own; the chains then run
+    one per process on the host cores and their wall time gives
+    proposals/s.  Runs in the background while the GPU
+    does other work."""
+
+    def __init__(self, slices, params, cfg, procs):
+        self.procs = procs
+        self.tmp = tempfile.TemporaryDirectory(prefix="pila_cpu_")
+        by_key = {}
+        for c, sl in enumerate(slices):
+            if sl.N <= 256:
+                by_key.setdefault((sl.N, sl.U, sl.K), []).append(c)
+        self.keys = sorted(by_key)
+        self.chains = []
+        M = cfg["M"]
+        picks = []
+        i = 0
+        while len(picks) < 2 * procs and any(i < len(v) for v in by_key.values()):
+            picks += [(key, by_key[key][i]) for key in self.keys if i < len(by_key[key])]
+            i += 1
+        for key, c in picks[:2 * procs]:
+            F = 4.0 / math.pi * key[1]  # mean row length
+            steps = int(min(params[c].n_steps, 1.5e8 / (M * F)))
+            p = params[c]
+            kw = dict(seed=p.seed, chain_id=p.chain_id, n_steps=steps, n_stages=p.n_stages,
+                      m_cand=p.m_cand, T0=None, q_auto=p.q_auto, tn_ratio=p.tn_ratio,
+                      delta_max=p.delta_max, f_min=p.f_min, f_max=p.f_max, precision="f32",
+                      resync_every=p.resync_every)
+            self.chains.append((key, slices[c].sino, slices[c].f0, kw, steps * M))
+        self.ex = _pool(procs)
+
+    def start(self):
+        import threading
+        self.result = None
+
+        def work():
+            t0 = time.perf_counter()
+            where = {k: os.path.join(self.tmp.name, "%d_%d_%d" % k) for k in self.keys}
+            list(self.ex.map(_cpu_pila, [(k[0], k[1], k[2], where[k]) for k in self.keys]))
+            t_build = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            secs = list(self.ex.map(_cpu_chain, [(where[k], k[0], k[1], k[2], s, f, kw)
+                                                 for k, s, f, kw, _ in self.chains]))
+            wall = time.perf_counter() - t1
+            props = sum(c[4] for c in self.chains)
+            used = min(self.procs, len(self.chains))
+            self.result = {
+                "value": props / wall, "unit": "proposals/s", "cores": used, "kind": "oracle",
+                "sample": "%d chains of the batch (from its 128^2 and 256^2 geometries: %s), each cut "
+                          "to its first steps (about 1.5e8 row entries of work; %d proposals in all), "
+                          "one process per chain on %d host cores, %.1f s wall (%.1f s of chain CPU "
+                          "time); oracle PILAs built beforehand in %.1f s, not timed"
+                          % (len(self.chains), ", ".join("%dx%d" % (k[0], k[1]) for k in self.keys),
+                             props, used, wall, sum(secs), t_build),
+                "cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+        self.thread = threading.Thread(target=work, daemon=True)
+        self.thread.start()
+
+    def finish(self):
+        self.thread.join()
+        self.ex.shutdown()
+        self.tmp.cleanup()
+        return self.result
+
+
+# ---------------------------------------------------------------------------
+# the batch benchmark line
+# ---------------------------------------------------------------------------
+
+def run_c3(args) -> int:
+    import torch
+    import datagen
+    import paper_1411_4622_amd as P
+    from bench_workloads import _params
+    from paper_1411_4622_amd.tune import tune_batch
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = datagen.CONFIGS["c3"]
+    n = args.slices
+    sweeps = cfg["sweeps"] if args.sweeps is None else args.sweeps
+    M = cfg["M"]
+    t0 = time.perf_counter()
+    specs = datagen.batch_slice_specs(cfg["volume_seed"], n, cfg["sizes"], cfg["n_angles"], cfg["I0"],
+                                      cfg["masked"])
+    with _pool(16) as ex:
+        slices = list(ex.map(datagen.slice_from_spec, specs, chunksize=4))
+    log("c3: %d slices generated in %.1f s" % (len(slices), time.perf_counter() - t0))
+    keys = sorted({(sl.N, sl.U) for sl in slices})
+    geoms = {}
+    for sl in slices:
+        if (sl.N, sl.U) not in geoms:
+            geoms[(sl.N, sl.U)] = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    sinos = [torch.from_numpy(sl.sino).to(dev) for sl in slices]
+    f0s = [torch.from_numpy(sl.f0).to(dev) for sl in slices]
+    imgs = [torch.empty_like(f) for f in f0s]
+    pilas = {k: P.pila_build(geoms[k]) for k in keys}
+    nnz = {k: pilas[k].nnz for k in keys}
+    fmean = {k: pilas[k].nnz / pilas[k].n_support for k in keys}
+    params = [_params(P, cfg, round(sweeps * int(sl.mask.sum())), cfg["chain_seed0"] + c, c,
+                      nnz=nnz[(sl.N, sl.U)]) for c, sl in enumerate(slices)]
+    steps_total = sum(p.n_steps for p in params)
+    key_of = [(sl.N, sl.U) for sl in slices]
+
+    def jobs_for(pl, dtype="f32", prm=None):
+        return [P.Job(pl[key_of[c]], sinos[c], imgs[c], (prm or params)[c]) for c in range(n)]
+
+    for c in range(n):
+        imgs[c].copy_(f0s[c])
+    (waves, per_cu), table = tune_batch(jobs_for(pilas), sample_steps=4096)
+    log("c3: launch shape %d waves/chain, %d chains/CU (tuned: %s)"
+        % (waves, per_cu, ", ".join("(%d,%d) %.3g/s" % (r["waves_per_chain"], r["chains_per_cu"],
+                                                       r["proposals_per_s"]) for r in table)))
+    del pilas
+
+    def one_step():
+        pl = {k: P.pila_build(geoms[k]) for k in keys}
+        for c in range(n):
+            imgs[c].copy_(f0s[c])
+        groups = []
+        st = P.sat_run_batch(jobs_for(pl), waves_per_chain=waves, chains_per_cu=per_cu, groups=groups)
+        return st, groups
+
+    for w in range(args.warmup):
+        ts = time.perf_counter()
+        one_step()
+        log("warmup %d/%d: %.2f s" % (w + 1, args.warmup, time.perf_counter() - ts))
+    torch.cuda.synchronize()
+    lat_step, group_runs = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        st, groups = one_step()
+        torch.cuda.synchronize()
+        lat_step.append(time.perf_counter() - ts)
+        group_runs.append(groups)
+        log("step %d/%d: %.2f s (groups: %s)" % (k + 1, args.steps, lat_step[-1],
+                                                 ", ".join("%d/%d,%d x%d %.0f ms" % (g["kind"], g["cpw"], g["e"],
+                                                                                   g["chains"], g["ms"])
+                                                           for g in groups)))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    proposals = args.steps * steps_total * M
+    value = proposals / wall
+    f32_imgs = [im.cpu().numpy() for im in imgs]
+
+    # per-slice latency inside the batch: device clock from the batch's first
+    # chain start to each chain's end
+    info = P.device_info()
+    rate = info["wallclock_khz"] * 1e3
+    t_first = min(s["t_begin"] for s in st)
+    lat_slice = np.array([(s["t_end"] - t_first) / rate for s in st])
+
+    # the plain one-chain form: each geometry's chain alone (sat_run), cut to
+    # its first 100k steps, then the serial time of all chains at those rates
+    lone_us = {}
+    for key in keys:
+        c = key_of.index(key)
+        steps1 = min(params[c].n_steps, 100_000)
+        pl = P.pila_build(geoms[key])
+        im = f0s[c].clone()
+        prm1 = _params(P, cfg, steps1, cfg["chain_seed0"] + c, c, nnz=nnz[key])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.sat_run(pl, sinos[c], prm1, im, stats=False)
+        e1.record()
+        e1.synchronize()
+        lone_us[key] = 1e3 * e0.elapsed_time(e1) / steps1
+    serial_s = sum(params[c].n_steps * lone_us[key_of[c]] / 1e6 for c in range(n))
+    log("c3: lone chains %s us/step; serial time of the batch's chains %.1f s"
+        % (", ".join("%dx%d %.2f" % (k[0], k[1], v) for k, v in sorted(lone_us.items())), serial_s))
+
+    # CPU oracle in the background while the GPU runs the FP64 reference batch
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu_job = CpuBaseline(slices, params, cfg, procs=min(16, os.cpu_count() or 1))
+        cpu_job.start()
+
+    ratios, rm64 = None, None
+    if not args.no_fp64_reference:
+        log("c3: FP64 batch with the same seeds (untimed)")
+        ts = time.perf_counter()
+        g64 = {k: P.Geometry(geoms[k].n, geoms[k].angles, geoms[k].n_bins, geoms[k].mask, "f64") for k in keys}
+        pl64 = {k: P.pila_build(g64[k]) for k in keys}
+        prm64 = [_params(P, cfg, params[c].n_steps, cfg["chain_seed0"] + c, c, "f64") for c in range(n)]
+        for c in range(n):
+            imgs[c].copy_(f0s[c])
+        P.sat_run_batch(jobs_for(pl64, prm=prm64), waves_per_chain=8, chains_per_cu=1, stats=False)
+        torch.cuda.synchronize()
+        rm64 = [datagen.rmse(imgs[c].cpu().numpy(), slices[c].truth) for c in range(n)]
+        del pl64
+        log("c3: FP64 batch in %.1f s" % (time.perf_counter() - ts))
+
+    # the noise-free 64 x 64 check of section III-B: U = 60, N_e = 16, 2e6
+    # steps over 1000 stages, Eq. 8 T0.  Noise-free here means data that the
+    # pixel model can fit: the projections of the phantom's pixel image by
+    # Eq. 1 (the exact line integrals of the continuous ellipses differ from
+    # any pixel image's by a floor, cost 0.25 at this size).
+    sanity = None
+    if not args.no_sanity:
+        N0, U0 = 64, 60
+        K0 = datagen.n_bins_for(N0)
+        ell = datagen.random_ellipses(106, N0, 10)
+        sl0 = datagen.make_slice(N0, U0, K0, ell, masked=True, I0=None)
+        pl0 = P.pila_build(P.Geometry(N0, sl0.angles, K0, sl0.mask, "f64"))
+        truth0 = torch.from_numpy(sl0.truth * sl0.mask).to(dev)
+        sino0 = P.pila_forward(pl0, truth0)
+        f00 = torch.from_numpy(datagen.uniform_start(sino0.cpu().numpy(), sl0.mask, N0)).to(dev)
+        im0 = f00.clone()
+        p0 = P.SatParams(n_steps=2_000_000, seed=1006, chain_id=0, n_stages=1000, m_cand=16, T0=None,
+                         q_auto=200, delta_max=0.05)
+        ts = time.perf_counter()
+        st0, _ = P.sat_run(pl0, sino0, p0, im0)
+        torch.cuda.synchronize()
+        f_s = im0.cpu().numpy()
+        t_s = truth0.cpu().numpy()
+        sanity = {"setting": "64x64 phantom of 10 ellipses, its pixel image projected by Eq. 1 (noise-free, "
+                             "consistent data), U=60, K=91, circular support, N_e=16, 2e6 steps over 1000 "
+                             "stages, change in [-0.05, 0.05) clamped to [0, 1], Eq. 8 T0, FP64",
+                  "nrmse": datagen.nrmse(f_s, t_s), "rmse": datagen.rmse(f_s, t_s),
+                  "cost_final": st0["cost_final"],
+                  "paper": "NRMSE below 5% after N=200 of 1000 stages (section III-B, on its phantom)",
+                  "seconds": time.perf_counter() - ts}
+        log("c3: section III-B check: NRMSE %.4f" % sanity["nrmse"])
+
+    if not args.no_cpu_baseline:
+        cpu = cpu_job.finish()
+        log("c3: cpu baseline %.3g proposals/s on %d cores" % (cpu["value"], cpu["cores"]))
+
+    # roofline of the group kernel that runs longest (its chains' algorithmic
+    # bytes over its duration from HIP events on its stream, averaged over
+    # the timed steps); the whole batch beside it
+    body_of = [s["body"] for s in st]
+    acc = [s["accepts"] for s in st]
+    b_chain = [chain_bytes(params[c].n_steps, M, fmean[key_of[c]], acc[c]) for c in range(n)]
+    gdesc = [(g["kind"], g["cpw"], g["e"]) for g in group_runs[-1]]
+    g_ms = {d: statistics.mean(next(g["ms"] for g in run if (g["kind"], g["cpw"], g["e"]) == d)
+                                for run in group_runs) for d in gdesc}
+    dom = max(g_ms, key=g_ms.get)
+
+    def in_group(body, d):
+        return (body & 15) == d[0] and ((body >> 8) & 255) == d[1] and ((body >> 16) & 255) == d[2]
+
+    dom_chains = [c for c in range(n) if in_group(body_of[c], dom)]
+    dom_bytes = sum(b_chain[c] for c in dom_chains)
+    achieved = dom_bytes / (g_ms[dom] / 1e3) / 1e9
+    kname = {1: "sat_batch_kernel<float,%d,%d>" % (dom[1], dom[2]), 2: "sat_batch_long_kernel<float,16>",
+             3: "sat_batch_simple_kernel"}[dom[0]]
+    traffic = None
+    if TRAFFIC and TRAFFIC.get("sources_sha256") == sources_hash() and TRAFFIC.get("kernel") == kname \
+            and args.slices == 512 and args.sweeps is None:
+        traffic = TRAFFIC["bytes_per_dispatch"]
+    rm32 = [datagen.rmse(f32_imgs[c], slices[c].truth) for c in range(n)]
+    nrm32 = [datagen.nrmse(f32_imgs[c], slices[c].truth) for c in range(n)]
+    ratio = [rm32[c] / rm64[c] for c in range(n)] if rm64 else None
+    out = {
+        "metric": "SA proposals evaluated/s + slices/s at fixed RMSE; p50/p99 slice latency",
+        "value": value,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: 512 slices of a seeded 32-ellipsoid volume, analytic line integrals, "
+                "Poisson noise I0=1e4",
+        "config": {"workload": "batch of %d independent slices in persistent launches: N in {128,256,512}, "
+                               "U in {90,180,360}, K=ceil(sqrt2 N), circular support, BoME M=8, %g sweeps "
+                               "(steps = sweeps x support), FP32 residual with FP64 resync, Eq. 8 T0, "
+                               "tuned launch shape" % (n, sweeps),
+                   "n_slices": n, "sweeps": sweeps, "M": M, "steps_total": steps_total,
+                   "geometries": {"%dx%d" % k: key_of.count(k) for k in keys}},
+        "steps_per_s": args.steps * steps_total / wall,
+        "slices_per_s": args.steps * n / wall,
+        "latency_s_p50": float(np.percentile(lat_slice, 50)),
+        "latency_s_p99": float(np.percentile(lat_slice, 99)),
+        "latency_note": "per slice inside one batch: device clock from the batch's first chain start "
+                        "to the slice's chain end",
+        "batch_s_per_step": statistics.mean(lat_step),
+        "rmse_fp32_mean": statistics.mean(rm32),
+        "nrmse_fp32_mean": statistics.mean(nrm32),
+        "rmse_ratio_fp32_fp64": None if ratio is None else
+        {"slices": len(ratio), "min": min(ratio), "max": max(ratio), "mean": statistics.mean(ratio),
+         "within_1pct": sum(1 for r in ratio if abs(r - 1.0) <= 0.01)},
+        "max_drift_r": max(s["max_drift_r"] for s in st),
+        "max_drift_sse": max(s["max_drift_sse"] for s in st),
+        "resyncs": sum(s["resyncs"] for s in st),
+        "batch_over_single": {"value": serial_s / (wall / args.steps), "serial_s": serial_s,
+                              "lone_us_per_step": {"%dx%d" % k: v for k, v in sorted(lone_us.items())},
+                              "how": "the same chains one at a time with sat_run, each geometry's "
+                                     "per-step time from its first 100k steps"},
+        "launch": {"waves_per_chain": waves, "chains_per_cu": per_cu, "tuner": table,
+                   "groups": group_runs[-1]},
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": g_ms[dom], "algorithmic_bytes_per_launch": dom_bytes,
+                     "chains": len(dom_chains),
+                     "batch_achieved_gbs": sum(b_chain) / (wall / args.steps) / 1e9},
+        "cpu_baseline": cpu,
+        "sanity_section_3b": sanity,
+        "device": info,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--chain-steps", type=int, default=None,
-                    help="override the chain length (profiling runs); the reported config says so")
-    ap.add_argument("--cpu-steps", type=int, default=1_000_000)
+    ap.add_argument("--workload", default="c3", choices=("c2", "c3", "c3r", "c4", "c5"),
+                    help="c3 (default): the batch line; c2: one chain; c3r: batch with repeated "
+                         "phantoms; c4: 1024^2 slice, SAT M=32 and SIRT; c5: serving stream")
+    ap.add_argument("--slices", type=int, default=512, help="c3: slices in the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-sanity", action="store_true")
+    ap.add_argument("--chain-steps", type=int, default=None,
+                    help="c2: override the chain length (profiling runs); the reported config says so")
+    ap.add_argument("--cpu-steps", type=int, default=1_000_000, help="c2: oracle steps timed")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (counter "
                          "calibration for rocprofv3 --pmc runs)")
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
-                    help="c2 (default): the single-chain benchmark line; c3: batch of slices; "
-                         "c4: 1024^2 slice, SAT M=32 and SIRT; c5: serving stream")
-    ap.add_argument("--slices", type=int, default=512, help="c3: slices in the batch")
-    ap.add_argument("--distinct", type=int, default=64,
-                    help="c3: distinct phantoms generated (the rest repeat them with other seeds)")
+    ap.add_argument("--distinct", type=int, default=64, help="c3r: distinct phantoms generated")
     ap.add_argument("--requests", type=int, default=2000, help="c5: requests in the stream")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: arrivals per second")
     ap.add_argument("--sweeps", type=float, default=None, help="c3/c5: steps = sweeps x support")
@@ -137,153 +480,15 @@ def main() -> int:
         print("bench.py runs on one GPU: an annealing chain does not shard across GPUs, and this "
               "build measures the one-GPU path only (--gpus 1).", file=sys.stderr)
         return 2
-    if args.workload != "c2":
-        import bench_workloads
-        return bench_workloads.run(args)
-
-    import torch
-    import datagen
-    import paper_1411_4622_amd as P
-
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    cfg = dict(datagen.CONFIGS["c2"])
-    if args.chain_steps:
-        cfg["n_steps"] = int(args.chain_steps)
-    log("input: c2 slice (analytic ellipse sinogram + Poisson noise)")
-    sl = datagen.config_slice("c2")
-    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
-    sino = torch.from_numpy(sl.sino).to(dev)
-    f0 = torch.from_numpy(sl.f0).to(dev)
-    img = torch.empty_like(f0)
-    prm = P.SatParams(n_steps=cfg["n_steps"], seed=cfg["chain_seed"], chain_id=0,
-                      n_stages=cfg["n_stages"], m_cand=cfg["M"], T0=None, q_auto=cfg["q_auto"],
-                      precision="f32", tn_ratio=cfg["tn_ratio"], delta_max=cfg["delta_max"],
-                      f_min=cfg["f_min"], f_max=cfg["f_max"], resync_every=cfg["resync_every"])
-    ws = P.sat_workspace(geom, prm, dev)
-    stream = torch.cuda.current_stream()
-
-    kernel_ms = []
-    launch_stats = []
-    last = {}
-
-    def one_step():
-        pl = P.pila_build(geom)
-        img.copy_(f0)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        st, _ = P.sat_run(pl, sino, prm, img, workspace=ws)
-        e1.record(stream)
-        e1.synchronize()
-        kernel_ms.append(e0.elapsed_time(e1))
-        launch_stats.append((st["chain_launches"], st["chain_kernel_ms"]))
-        last["stats"] = st
-        last["pila"] = (pl.nnz, pl.n_support)
-
-    for w in range(args.warmup):
-        one_step()
-        log("warmup %d/%d: chain %.1f ms" % (w + 1, args.warmup, kernel_ms[-1]))
-    kernel_ms.clear()
-    launch_stats.clear()
-    torch.cuda.synchronize()
-    lat = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        one_step()
-        lat.append(time.perf_counter() - ts)
-        log("step %d/%d: %.3f s (chain kernel %.1f ms)" % (k + 1, args.steps, lat[-1], kernel_ms[-1]))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    st = last["stats"]
-    nnz, P_sup = last["pila"]
-    proposals = args.steps * cfg["n_steps"] * cfg["M"]
-    value = proposals / wall
-    f32_img = img.cpu().numpy()
-    rmse32 = datagen.rmse(f32_img, sl.truth)
-
-    rmse64 = None
-    if not args.no_fp64_reference:
-        log("fp64 reference chain (same seeds, untimed)")
-        g64 = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f64")
-        pl64 = P.pila_build(g64)
-        img64 = f0.clone()
-        p64 = P.SatParams(**{**prm.__dict__, "precision": "f64", "resync_every": 0})
-        P.sat_run(pl64, sino, p64, img64)
-        torch.cuda.synchronize()
-        rmse64 = datagen.rmse(img64.cpu().numpy(), sl.truth)
-        del pl64
-
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: %d MiB read + %d MiB written per copy, 3 copies"
-            % (args.copy_probe_mib, args.copy_probe_mib))
-        del src, dst
-
-    f_mean = nnz / P_sup
-    # chain-kernel launches of the timed steps, each timed by the library with
-    # HIP events on the chain's stream; every step runs the same chain
-    launches = max(int(st["chain_launches"]), 1)
-    launch_s = sum(ms for _, ms in launch_stats) / 1e3 / max(sum(n for n, _ in launch_stats), 1)
-    alg_bytes = chain_kernel_bytes(cfg["n_steps"], cfg["M"], f_mean, st["accepts"]) / launches
-    achieved = alg_bytes / launch_s / 1e9
-    traffic = None
-    if TRAFFIC and TRAFFIC.get("sources_sha256") == sources_hash() and not args.chain_steps:
-        traffic = TRAFFIC["bytes_per_launch"]
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(sl, cfg, args.cpu_steps)
-
-    info = P.device_info()
-    out = {
-        "metric": "SA proposals evaluated/s + slices/s at fixed RMSE; p50/p99 slice latency",
-        "value": value,
-        "unit": "proposals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic: seeded 10-ellipse phantom, analytic line integrals, Poisson noise I0=1e4",
-        "config": {"workload": "single SA chain, 256x256 slice, 180 angles, 367 bins, circular "
-                               "support, BoME M=16, %d steps, FP32 residual with FP64 resync every "
-                               "4096 accepts, Eq. 8 T0" % cfg["n_steps"],
-                   "N": sl.N, "U": sl.U, "K": sl.K, "M": cfg["M"], "n_steps": cfg["n_steps"]},
-        "steps_per_s": args.steps * cfg["n_steps"] / wall,
-        "slices_per_s": args.steps / wall,
-        "latency_s_p50": float(np.percentile(lat, 50)),
-        "latency_s_p99": float(np.percentile(lat, 99)),
-        "rmse_fp32": rmse32,
-        "rmse_fp64": rmse64,
-        "rmse_ratio_fp32_fp64": (rmse32 / rmse64) if rmse64 else None,
-        "nrmse_fp32": rmse32 / float(np.mean(sl.truth)),
-        "chain": {"accepts": st["accepts"], "accepts_nonzero": st["accepts_nonzero"],
-                  "resyncs": st["resyncs"], "T0": st["T0_used"], "max_drift_r": st["max_drift_r"],
-                  "max_drift_sse": st["max_drift_sse"], "cost_final": st["cost_final"]},
-        "roofline": {"kernel": "sat_segment_kernel (one launch per resync segment of the chain)",
-                     "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "launches_per_step": launches,
-                     "avg_launch_ms": 1e3 * launch_s,
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "chain_ms_per_step": statistics.mean(kernel_ms)},
-        "cpu_baseline": cpu,
-        "device": info,
-    }
-    print(json.dumps(out), flush=True)
-    return 0
+    if args.workload == "c3":
+        rc = run_c3(args)
+        if args.copy_probe_mib > 0:
+            import torch
+            import bench_workloads
+            bench_workloads.copy_probe(args, torch)
+        return rc
+    import bench_workloads
+    return bench_workloads.run(args)
 
 
 if __name__ == "__main__":

@@ -1,6 +1,9 @@
-"""Workloads beside the single-chain benchmark line (bench.py --workload ...).
+"""Workloads beside the batch benchmark line (bench.py --workload ...).
 
-c3  batch: slices cut from one seeded ellipsoid volume (N in {128, 256, 512},
+c2  one chain: 256 x 256 slice, 180 angles, 367 bins, M = 16, 5e6 steps, FP32
+    residual against an FP64 chain with the same seeds.
+
+c3r batch with repeated phantoms: slices cut from one seeded ellipsoid volume (N in {128, 256, 512},
     90/180/360 angles, K = ceil(sqrt(2) N), Poisson noise I0 = 1e4, circular
     support), M = 8, FP32 residual with FP64 resync every 4096 accepted
     nonzero changes, 16 sweeps of the support, all chains in one persistent
@@ -18,6 +21,7 @@ Every input is synthetic and seeded.  Each workload prints one JSON line.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -82,10 +86,216 @@ def _chain_bytes(n_steps, M, f_mean, accepts):
 
 
 # ---------------------------------------------------------------------------
-# c3: batch
+# c2: one chain, FP32 residual against FP64
 # ---------------------------------------------------------------------------
 
-def run_c3(args, P, torch, datagen):
+def chain_kernel_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
+    """Algorithmic bytes of the chain kernel over a whole chain (FP32 PILA and residual).
+
+    per estimate: support index 4, image value 8, row offsets 16, and per row
+    entry ray index 4 + length 4 + residual 4; per accepted estimate: per row
+    entry ray index 4 + length 4 + residual read 4 + write 4, image write 8.
+    The FP64 rebuilds at the resyncs (per PILA entry pixel index 4 + length 4
+    + image value 8, per ray 32) run in their own kernel and are not counted.
+    """
+    return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
+
+
+# HBM bytes per chain-kernel launch from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# runs of this benchmark, each scaled by the factor that makes the counter
+# read the known size of a plain device copy in the same run; valid only for
+# the kernel sources they were taken with (hash over the files below)
+TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
+                   "paper_1411_4622_amd/csrc/common.hpp")
+TRAFFIC = {"sources_sha256": "cec2281accac605fc0998dce270a3680c42776dae036492060191677cfa4a570",
+           "bytes_per_launch": 143386283.5}
+
+
+def sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cpu_baseline_c2(sl, cfg, n_steps_cpu: int) -> dict:
+    import oracle
+    log("cpu baseline: oracle PILA for %dx%d, %d angles" % (sl.N, sl.N, sl.U))
+    csr = oracle.pila(sl.N, sl.U, sl.K, sl.angles, sl.mask)
+    kw = dict(seed=cfg["chain_seed"], chain_id=0, n_steps=n_steps_cpu, n_stages=cfg["n_stages"],
+              m_cand=cfg["M"], T0=None, q_auto=cfg["q_auto"], tn_ratio=cfg["tn_ratio"],
+              delta_max=cfg["delta_max"], f_min=cfg["f_min"], f_max=cfg["f_max"],
+              precision=cfg["precision"], resync_every=cfg["resync_every"])
+    log("cpu baseline: oracle chain, %d steps" % n_steps_cpu)
+    t0 = time.perf_counter()
+    oracle.sat_run(sl.N, sl.U, sl.K, csr, sl.sino, sl.f0, mask=sl.mask, trace=False, **kw)
+    dt = time.perf_counter() - t0
+    return {"value": n_steps_cpu * cfg["M"] / dt, "unit": "proposals/s", "cores": 1, "kind": "oracle",
+            "sample": "the same chain (same slice, M, FP32 residual with FP64 resync) cut to its "
+                      "first %d of %d steps, single thread, %.1f s; PILA build not timed"
+                      % (n_steps_cpu, cfg["n_steps"], dt),
+            "cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+
+def run_c2(args, P, torch, datagen):
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = dict(datagen.CONFIGS["c2"])
+    if args.chain_steps:
+        cfg["n_steps"] = int(args.chain_steps)
+    log("input: c2 slice (analytic ellipse sinogram + Poisson noise)")
+    sl = datagen.config_slice("c2")
+    geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+    sino = torch.from_numpy(sl.sino).to(dev)
+    f0 = torch.from_numpy(sl.f0).to(dev)
+    img = torch.empty_like(f0)
+    prm = P.SatParams(n_steps=cfg["n_steps"], seed=cfg["chain_seed"], chain_id=0,
+                      n_stages=cfg["n_stages"], m_cand=cfg["M"], T0=None, q_auto=cfg["q_auto"],
+                      precision="f32", tn_ratio=cfg["tn_ratio"], delta_max=cfg["delta_max"],
+                      f_min=cfg["f_min"], f_max=cfg["f_max"], resync_every=cfg["resync_every"])
+    ws = P.sat_workspace(geom, prm, dev)
+    stream = torch.cuda.current_stream()
+
+    kernel_ms = []
+    launch_stats = []
+    last = {}
+
+    def one_step():
+        pl = P.pila_build(geom)
+        img.copy_(f0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st, _ = P.sat_run(pl, sino, prm, img, workspace=ws)
+        e1.record(stream)
+        e1.synchronize()
+        kernel_ms.append(e0.elapsed_time(e1))
+        launch_stats.append((st["chain_launches"], st["chain_kernel_ms"]))
+        last["stats"] = st
+        last["pila"] = (pl.nnz, pl.n_support)
+
+    for w in range(args.warmup):
+        one_step()
+        log("warmup %d/%d: chain %.1f ms" % (w + 1, args.warmup, kernel_ms[-1]))
+    kernel_ms.clear()
+    launch_stats.clear()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        one_step()
+        lat.append(time.perf_counter() - ts)
+        log("step %d/%d: %.3f s (chain kernel %.1f ms)" % (k + 1, args.steps, lat[-1], kernel_ms[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    st = last["stats"]
+    nnz, P_sup = last["pila"]
+    proposals = args.steps * cfg["n_steps"] * cfg["M"]
+    value = proposals / wall
+    f32_img = img.cpu().numpy()
+    rmse32 = datagen.rmse(f32_img, sl.truth)
+
+    rmse64 = None
+    if not args.no_fp64_reference:
+        log("fp64 reference chain (same seeds, untimed)")
+        g64 = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f64")
+        pl64 = P.pila_build(g64)
+        img64 = f0.clone()
+        p64 = P.SatParams(**{**prm.__dict__, "precision": "f64", "resync_every": 0})
+        P.sat_run(pl64, sino, p64, img64)
+        torch.cuda.synchronize()
+        rmse64 = datagen.rmse(img64.cpu().numpy(), sl.truth)
+        del pl64
+
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB read + %d MiB written per copy, 3 copies"
+            % (args.copy_probe_mib, args.copy_probe_mib))
+        del src, dst
+
+    f_mean = nnz / P_sup
+    # chain-kernel launches of the timed steps, each timed by the library with
+    # HIP events on the chain's stream; every step runs the same chain
+    launches = max(int(st["chain_launches"]), 1)
+    launch_s = sum(ms for _, ms in launch_stats) / 1e3 / max(sum(n for n, _ in launch_stats), 1)
+    alg_bytes = chain_kernel_bytes(cfg["n_steps"], cfg["M"], f_mean, st["accepts"]) / launches
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = None
+    if TRAFFIC and TRAFFIC.get("sources_sha256") == sources_hash() and not args.chain_steps:
+        traffic = TRAFFIC["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_c2(sl, cfg, args.cpu_steps)
+
+    info = P.device_info()
+    out = {
+        "metric": "SA proposals evaluated/s + slices/s at fixed RMSE; p50/p99 slice latency",
+        "value": value,
+        "unit": "proposals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded 10-ellipse phantom, analytic line integrals, Poisson noise I0=1e4",
+        "config": {"workload": "single SA chain, 256x256 slice, 180 angles, 367 bins, circular "
+                               "support, BoME M=16, %d steps, FP32 residual with FP64 resync every "
+                               "4096 accepts, Eq. 8 T0" % cfg["n_steps"],
+                   "N": sl.N, "U": sl.U, "K": sl.K, "M": cfg["M"], "n_steps": cfg["n_steps"]},
+        "steps_per_s": args.steps * cfg["n_steps"] / wall,
+        "slices_per_s": args.steps / wall,
+        "latency_s_p50": float(np.percentile(lat, 50)),
+        "latency_s_p99": float(np.percentile(lat, 99)),
+        "rmse_fp32": rmse32,
+        "rmse_fp64": rmse64,
+        "rmse_ratio_fp32_fp64": (rmse32 / rmse64) if rmse64 else None,
+        "nrmse_fp32": rmse32 / float(np.mean(sl.truth)),
+        "chain": {"accepts": st["accepts"], "accepts_nonzero": st["accepts_nonzero"],
+                  "resyncs": st["resyncs"], "T0": st["T0_used"], "max_drift_r": st["max_drift_r"],
+                  "max_drift_sse": st["max_drift_sse"], "cost_final": st["cost_final"]},
+        "roofline": {"kernel": "sat_segment_kernel (one launch per resync segment of the chain)",
+                     "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "launches_per_step": launches,
+                     "avg_launch_ms": 1e3 * launch_s,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "chain_ms_per_step": statistics.mean(kernel_ms)},
+        "cpu_baseline": cpu,
+        "device": info,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# c3 with repeated phantoms (the default benchmark line is bench.run_c3)
+# ---------------------------------------------------------------------------
+
+def run_c3_repeat(args, P, torch, datagen):
     from paper_1411_4622_amd.tune import tune_batch
     cfg = datagen.CONFIGS["c3"]
     sweeps = args.sweeps if args.sweeps is not None else cfg["sweeps"]
@@ -419,4 +629,5 @@ def run(args) -> int:
     import paper_1411_4622_amd as P
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    return {"c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args, P, torch, datagen)
+    return {"c2": run_c2, "c3r": run_c3_repeat, "c4": run_c4,
+            "c5": run_c5}[args.workload](args, P, torch, datagen)

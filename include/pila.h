@@ -63,7 +63,9 @@ extern "C" {
 #define PILA_PROP_REDRAW 1  /* the change is drawn again until the value is in range
                                (Step 2, Eq. 3 as printed) */
 
-/* which chain body ran a chain (sat_stats.body): a kind plus flags */
+/* which chain body ran a chain (sat_stats.body): a kind plus flags, and for the
+ * pipelined body its register shape: estimates per wavefront << 8 | row
+ * entries per lane << 16 */
 #define PILA_BODY_PIPED 1     /* rows in registers, estimates drawn ahead */
 #define PILA_BODY_LONG 2      /* rows of more than 512 entries, one estimate per wavefront */
 #define PILA_BODY_GENERAL 3   /* any row length and M, draws at the step (needed for redraw) */
@@ -191,6 +193,9 @@ typedef struct sat_stats {
     int32_t body;           /* PILA_BODY_* kind | flags of the body that ran the chain */
     double chain_kernel_ms; /* sat_run: summed duration of those launches, from
                                HIP events recorded around each of them */
+    int64_t t_begin, t_end; /* sat_run_batch and the server: device wall clock
+                               (pila_device_info.wallclock_khz) when the chain's
+                               workgroup took it and when it finished; 0 from sat_run */
 } sat_stats;
 
 /* Optional per-step record, device arrays of n_steps elements (each may be
@@ -268,13 +273,26 @@ typedef struct sat_launch {
     int32_t waves_per_chain; /* 1, 2, 4, 8 or 16 wavefronts per chain */
     int32_t chains_per_cu;   /* resident chains per compute unit */
     int32_t lds_residual;    /* 1: keep a chain's residual in LDS when it fits */
-    int32_t reserved;
+    int32_t max_groups;      /* room in the three arrays below (0: not wanted) */
+    /* out, per group of chains that one persistent kernel runs (unused
+     * entries get desc 0): the kernel's duration from HIP events recorded
+     * around it on its stream, its body (PILA_BODY_* kind | register shape:
+     * estimates per wavefront << 8 | row entries per lane << 16) and its chain
+     * count.  Host arrays; filled when the call returns. */
+    float* h_group_ms;
+    int32_t* h_group_desc;
+    int32_t* h_group_chains;
 } sat_launch;
 
 /*
  * sat_batch_workspace_size / sat_run_batch - many independent chains (one
- * per slice) in one persistent launch: one workgroup runs one chain at a
- * time and takes the next chain from a device ticket counter.  Each chain
+ * per slice) in persistent launches: one workgroup runs one chain at a
+ * time and takes the next chain from a device ticket counter.  Chains are
+ * grouped by body and register shape (each chain takes the pipelined body
+ * at the smallest shape that holds its rows, else the long-row or general
+ * body); each group is one persistent kernel, the groups run side by side
+ * on streams forked from the caller's and joined back into it, and a
+ * group hands out its longest chains first.  Each chain
  * computes exactly what sat_run computes for its job, independently of the
  * other jobs and of the launch shape's chain placement.  The call uploads
  * the chain descriptors from host memory it owns and synchronises the
@@ -438,6 +456,8 @@ typedef struct pila_device_info {
     int32_t warp_size;
     size_t hbm_bytes;
     char name[64];
+    int32_t wallclock_khz;   /* rate of the device wall clock of sat_stats.t_begin/t_end */
+    int32_t pad;
 } pila_device_info;
 
 int32_t pila_get_device_info(pila_device_info* info);

@@ -63,7 +63,8 @@ class CSatStats(C.Structure):
                 ("resyncs", C.c_int32), ("status", C.c_int32), ("T0_used", C.c_double),
                 ("TN_used", C.c_double), ("sse_final", C.c_double), ("cost_final", C.c_double),
                 ("max_drift_r", C.c_double), ("max_drift_sse", C.c_double),
-                ("chain_launches", C.c_int32), ("body", C.c_int32), ("chain_kernel_ms", C.c_double)]
+                ("chain_launches", C.c_int32), ("body", C.c_int32), ("chain_kernel_ms", C.c_double),
+                ("t_begin", C.c_int64), ("t_end", C.c_int64)]
 
 
 class CSatTrace(C.Structure):
@@ -77,7 +78,9 @@ class CSatJob(C.Structure):
 
 class CSatLaunch(C.Structure):
     _fields_ = [("waves_per_chain", C.c_int32), ("chains_per_cu", C.c_int32),
-                ("lds_residual", C.c_int32), ("reserved", C.c_int32)]
+                ("lds_residual", C.c_int32), ("max_groups", C.c_int32),
+                ("h_group_ms", C.POINTER(C.c_float)), ("h_group_desc", C.POINTER(C.c_int32)),
+                ("h_group_chains", C.POINTER(C.c_int32))]
 
 
 class CSirtParams(C.Structure):
@@ -103,7 +106,8 @@ class CSrvStatus(C.Structure):
 
 class CDeviceInfo(C.Structure):
     _fields_ = [("cu_count", C.c_int32), ("lds_per_block", C.c_int32), ("clock_khz", C.c_int32),
-                ("warp_size", C.c_int32), ("hbm_bytes", C.c_size_t), ("name", C.c_char * 64)]
+                ("warp_size", C.c_int32), ("hbm_bytes", C.c_size_t), ("name", C.c_char * 64),
+                ("wallclock_khz", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -389,9 +393,16 @@ class Job:
     params: SatParams
 
 
+MAX_GROUPS = 8
+
+
 def sat_run_batch(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: int = 2,
-                  lds_residual: bool = True, workspace=None, stats: bool = True):
-    """Many independent chains in one persistent launch; images updated in place."""
+                  lds_residual: bool = True, workspace=None, stats: bool = True,
+                  groups: Optional[list] = None):
+    """Many independent chains in persistent launches (one per group of chains
+    sharing a body and register shape, side by side); images updated in place.
+    groups (a list, optional) receives one dict per group: kernel duration in
+    ms from HIP events on its stream, body kind, register shape, chain count."""
     torch = _torch()
     n = len(jobs)
     cj = (CSatJob * max(n, 1))()
@@ -410,8 +421,23 @@ def sat_run_batch(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: int 
     ws = workspace if workspace is not None else torch.empty(int(nb.value), dtype=torch.uint8,
                                                              device="cuda")
     launch = CSatLaunch(waves_per_chain, chains_per_cu, 1 if lds_residual else 0, 0)
+    if groups is not None:
+        g_ms = (C.c_float * MAX_GROUPS)()
+        g_desc = (C.c_int32 * MAX_GROUPS)()
+        g_n = (C.c_int32 * MAX_GROUPS)()
+        launch.max_groups = MAX_GROUPS
+        launch.h_group_ms = C.cast(g_ms, C.POINTER(C.c_float))
+        launch.h_group_desc = C.cast(g_desc, C.POINTER(C.c_int32))
+        launch.h_group_chains = C.cast(g_n, C.POINTER(C.c_int32))
     st = (CSatStats * max(n, 1))() if stats else None
     _check(lib.sat_run_batch(n, cj, C.byref(launch), ws.data_ptr(), ws.numel(), st, _stream()))
+    if groups is not None:
+        groups.clear()
+        for i in range(MAX_GROUPS):
+            d = int(g_desc[i])
+            if d:
+                groups.append(dict(ms=float(g_ms[i]), kind=d & 255, cpw=(d >> 8) & 255,
+                                   e=(d >> 16) & 255, chains=int(g_n[i])))
     return [_stats_dict(st[i]) for i in range(n)] if stats else None
 
 
@@ -513,4 +539,5 @@ def device_info() -> dict:
     info = CDeviceInfo()
     _check(load().pila_get_device_info(C.byref(info)))
     return dict(cu_count=info.cu_count, lds_per_block=info.lds_per_block, clock_khz=info.clock_khz,
-                warp_size=info.warp_size, hbm_bytes=info.hbm_bytes, name=info.name.decode())
+                warp_size=info.warp_size, hbm_bytes=info.hbm_bytes, name=info.name.decode(),
+                wallclock_khz=info.wallclock_khz)

@@ -77,5 +77,8 @@ extern "C" int32_t pila_get_device_info(pila_device_info* info)
     info->warp_size = p.warpSize;
     info->hbm_bytes = p.totalGlobalMem;
     std::snprintf(info->name, sizeof(info->name), "%s", p.gcnArchName);
+    int wc = 0;
+    PILA_HIP(hipDeviceGetAttribute(&wc, hipDeviceAttributeWallClockRate, dev));
+    info->wallclock_khz = wc;
     return PILA_OK;
 }

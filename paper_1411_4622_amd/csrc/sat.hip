@@ -333,16 +333,27 @@ __global__ void sat_final_kernel(ChainJob job)
     st.chain_launches = 0;
     st.body = 0;
     st.chain_kernel_ms = 0.0;
+    st.t_begin = st.t_end = 0;
     *job.stats = st;
 }
 
 // Persistent batch: each workgroup takes chains from a ticket counter until
-// the tickets run out, so every workgroup reaches the exit.  This kernel
-// runs the FP32 chains whose rows and estimates fit the (CPW, E) shape with
-// the pipelined body, reading the slot words of their PILA's entries
-// (computed once per PILA and batch); the long-row and general kernels run
-// the others.  All give the result the chain would give alone.
-template <int CPW, int E>
+// the tickets run out, so every workgroup reaches the exit.  The pipelined
+// kernel runs chains whose rows and estimates fit its (CPW, E) shape; FP32
+// chains read the slot words of their PILA's entries (computed once per PILA
+// and batch), FP64 chains form them per entry.  The long-row and general
+// kernels run the others.  All give the result the chain would give alone.
+// Thread 0 stamps the device wall clock when the chain is taken and when it
+// is done into the chain's statistics.
+__device__ __forceinline__ void stamp_chain(const ChainJob& J, int64_t t0)
+{
+    if (threadIdx.x == 0 && J.stats) {
+        J.stats->t_begin = t0;
+        J.stats->t_end = (int64_t)wall_clock64();
+    }
+}
+
+template <typename Real, int CPW, int E>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
     const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
     int* __restrict__ ticket, int lds_bytes)
@@ -356,13 +367,15 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
         const int j = sh.ticket;
         __syncthreads();
         if (j >= n_jobs) break;
-        const ChainJob J = jobs[order[j]];
-        run_chain_piped<float, false, CPW, E, false, true>(J, lds, sh, false);
+        const int64_t t0 = (int64_t)wall_clock64();
+        const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
+        run_chain_piped<Real, false, CPW, E, false, sizeof(Real) == 4>(J, lds, sh, false);
+        stamp_chain(J, t0);
     }
 }
 
-// Persistent batch of long-row FP32 chains (one estimate per wavefront)
-template <int E>
+// Persistent batch of long-row chains (one estimate per wavefront)
+template <typename Real, int E>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_long_kernel(
     const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
     int* __restrict__ ticket, int lds_bytes)
@@ -376,13 +389,15 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_long_kernel(
         const int j = sh.ticket;
         __syncthreads();
         if (j >= n_jobs) break;
-        const ChainJob J = jobs[order[j]];
-        run_chain_long<float, false, E>(J, lds, sh, false);
+        const int64_t t0 = (int64_t)wall_clock64();
+        const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
+        run_chain_long<Real, false, E>(J, lds, sh, false);
+        stamp_chain(J, t0);
     }
 }
 
-// Persistent batch for workgroups wider than the pipelined bodies allow:
-// every chain takes the general body.
+// Persistent batch for the general body (any row length, M, precision or
+// proposal rule)
 __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* __restrict__ jobs,
                                                                 const int* __restrict__ order,
                                                                 int n_jobs, int* __restrict__ ticket,
@@ -396,11 +411,13 @@ __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* 
         const int j = sh.ticket;
         __syncthreads();
         if (j >= n_jobs) break;
-        const ChainJob J = jobs[order[j]];
+        const int64_t t0 = (int64_t)wall_clock64();
+        const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
         if (J.precision == PILA_F32)
             run_chain_simple_dispatch<float>(J, lds, lds_bytes, sh);
         else
             run_chain_simple_dispatch<double>(J, lds, lds_bytes, sh);
+        stamp_chain(J, t0);
     }
 }
 
@@ -468,12 +485,16 @@ struct BatchShape {
     BatchKernel k;
 };
 
-const std::vector<BatchShape>& batch_shapes()
+// the pipelined shapes of the batch kernels, per precision (FP64 rows hold
+// at most 256 entries in registers; longer FP64 rows take the long-row body)
+const std::vector<BatchShape>& batch_shapes(int precision)
 {
-    static const std::vector<BatchShape> v = {
-        {1, 4, sat_batch_kernel<1, 4>}, {1, 8, sat_batch_kernel<1, 8>}, {2, 8, sat_batch_kernel<2, 8>},
-        {4, 8, sat_batch_kernel<4, 8>}};
-    return v;
+    static const std::vector<BatchShape> f32 = {
+        {1, 4, sat_batch_kernel<float, 1, 4>}, {1, 8, sat_batch_kernel<float, 1, 8>},
+        {2, 8, sat_batch_kernel<float, 2, 8>}, {4, 8, sat_batch_kernel<float, 4, 8>}};
+    static const std::vector<BatchShape> f64 = {{1, 4, sat_batch_kernel<double, 1, 4>},
+                                                {2, 8, sat_batch_kernel<double, 2, 8>}};
+    return precision == PILA_F64 ? f64 : f32;
 }
 
 // HIP events around each chain-kernel launch of one sat_run, summed after
@@ -524,12 +545,13 @@ int32_t launch1(ChainKernel k, ChainJob* J, int threads, int lds, hipStream_t st
 using namespace pila;
 
 // Room for the slot words of every PILA entry (one int32 each) that the
-// pipelined FP32 body takes precomputed; offered for geometries of at most
-// 256 angles (rows of at most 2 U <= 512 entries), sized by the bound of two
-// rays per support pixel and angle.
+// pipelined FP32 body takes precomputed (without them its 8-entry shapes run
+// out of registers); offered for geometries of at most 512 angles (rows of
+// at most 512 entries, the pipelined body's limit, need U <= 512), sized by
+// the bound of two rays per support pixel and angle.
 size_t tcol_bytes(const pila_geom* g, const sat_params* p)
 {
-    if (p->precision != PILA_F32 || g->n_angles > 256) return 0;
+    if (p->precision != PILA_F32 || g->n_angles > 512) return 0;
     int64_t sup = (int64_t)g->n * g->n;
     if (g->mask) {
         sup = 0;
@@ -608,7 +630,8 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
     const int glob = r_in_lds ? 0 : PILA_BODY_GLOBAL_R;
     int body = 0;
     if (piped_seg || long_seg || simple_seg) {
-        body = (piped_seg ? PILA_BODY_PIPED : long_seg ? PILA_BODY_LONG : PILA_BODY_GENERAL) |
+        body = (piped_seg ? PILA_BODY_PIPED | (ps->cpw << 8) | (ps->e << 16)
+                          : long_seg ? PILA_BODY_LONG : PILA_BODY_GENERAL) |
                PILA_BODY_GLOBAL_R | PILA_BODY_SEGMENTED;
         // FP32 residual in global memory: chain segments end at each resync,
         // which runs grid-wide; the host only enqueues, it never waits
@@ -635,7 +658,7 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
         }
         sat_final_kernel<<<1, 1, 0, st>>>(J);
     } else if (ps && (r_in_lds || table_lds <= budget)) {
-        body = PILA_BODY_PIPED | glob;
+        body = PILA_BODY_PIPED | glob | (ps->cpw << 8) | (ps->e << 16);
         const int lds = r_in_lds ? (int)(G * rs) : table_lds;
         PILA_TRY(launch1(r_in_lds ? ps->k_lds : (tk ? ps->k_glob_tk : ps->k_glob), &J, waves * kWave, lds, st,
                          &tm));
@@ -855,12 +878,12 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     for (int32_t j = 0; j < n_jobs; ++j) {
         ChainJob& J = host[j];
         const bool ahead = J.proposal == PILA_PROP_CLAMP;
-        const bool f32 = ahead && J.precision == PILA_F32 && waves * kWave <= kPipedThreads;
+        const bool fits = ahead && waves * kWave <= kPipedThreads;
         const BatchShape* bs = nullptr;
-        if (f32 && piped_allowed(jobs[j].geom, jobs[j].csr)) {
+        if (fits && piped_allowed(jobs[j].geom, jobs[j].csr)) {
             for (int cpw : {1, 2, 4}) {
                 if (J.m_cand > waves * cpw) continue;
-                for (const BatchShape& sp : batch_shapes())
+                for (const BatchShape& sp : batch_shapes(J.precision))
                     if (sp.cpw == cpw && J.max_row <= (kWave / cpw) * sp.e) {
                         bs = &sp;
                         break;
@@ -872,13 +895,13 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         int kind = PILA_BODY_GENERAL;
         if (bs) {
             kind = PILA_BODY_PIPED;
-        } else if (f32 && J.m_cand <= waves && long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
+        } else if (fits && J.m_cand <= waves && long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
             long_lds(&J, lds);
             kind = PILA_BODY_LONG;
         } else {
             J.UL = 0;
         }
-        BatchGroup& g = group_of(kind, bs);
+        BatchGroup& g = group_of(kind | (J.precision == PILA_F64 ? 256 : 0), bs);
         g.ids.push_back(j);
         g.longest = std::max(g.longest, work(j));
     }
@@ -895,7 +918,7 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         const std::vector<const pila_csr*> tp = batch_tcol_pilas(n_jobs, jobs);
         std::vector<int32_t*> where(tp.size(), nullptr);
         for (const BatchGroup& g : groups) {
-            if (g.kind != PILA_BODY_PIPED) continue;
+            if (g.kind != PILA_BODY_PIPED) continue;  // FP32 pipelined groups only
             for (int j : g.ids) {
                 size_t i = 0;
                 while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
@@ -939,6 +962,19 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
             PILA_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
         }
     }
+    // HIP events around each group's kernel on its stream, when asked for
+    const bool timed = launch && launch->max_groups > 0 && launch->h_group_ms;
+    hipEvent_t t_ev[2 * kMaxGroups] = {};
+    struct TimingEvents {
+        hipEvent_t* e;
+        ~TimingEvents()
+        {
+            for (int i = 0; i < 2 * kMaxGroups; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } t_cleanup{t_ev};
+    if (timed)
+        for (size_t i = 0; i < 2 * groups.size(); ++i) PILA_HIP(hipEventCreate(&t_ev[i]));
     const ChainJob* jobs_arg = d_jobs;
     int lds_arg = lds;
     size_t first = 0;
@@ -951,11 +987,17 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         first += g.ids.size();
         void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
         const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
-        const void* k = g.kind == PILA_BODY_PIPED ? (const void*)g.shape->k
-                        : g.kind == PILA_BODY_LONG ? (const void*)sat_batch_long_kernel<kLongE>
-                                                   : (const void*)sat_batch_simple_kernel;
+        const int kind = g.kind & 255;
+        const bool f64 = (g.kind & 256) != 0;
+        const void* k = kind == PILA_BODY_PIPED ? (const void*)g.shape->k
+                        : kind == PILA_BODY_LONG
+                            ? (f64 ? (const void*)sat_batch_long_kernel<double, kLongE>
+                                   : (const void*)sat_batch_long_kernel<float, kLongE>)
+                            : (const void*)sat_batch_simple_kernel;
         PILA_TRY(set_lds(k, lds));
+        if (timed) PILA_HIP(hipEventRecord(t_ev[2 * gi], gs));
         PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, gs));
+        if (timed) PILA_HIP(hipEventRecord(t_ev[2 * gi + 1], gs));
         if (gi > 0) PILA_HIP(hipEventRecord(join[gi - 1], gs));
     }
     for (int i = 0; i < n_aux; ++i) PILA_HIP(hipStreamWaitEvent(st, join[i], 0));
@@ -971,9 +1013,26 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
             for (int j : g.ids) {
                 const ChainJob& J = host[j];
                 const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
-                const bool glob = g.kind != PILA_BODY_GENERAL || rb > lds;
-                h_stats[j].body = g.kind | (glob ? PILA_BODY_GLOBAL_R : 0);
+                const int kind = g.kind & 255;
+                const bool glob = kind != PILA_BODY_GENERAL || rb > lds;
+                h_stats[j].body = kind | (glob ? PILA_BODY_GLOBAL_R : 0) |
+                                  (g.shape ? (g.shape->cpw << 8) | (g.shape->e << 16) : 0);
             }
+    }
+    if (launch && launch->max_groups > 0) {
+        for (int i = 0; i < launch->max_groups; ++i) {
+            const bool have = i < (int)groups.size();
+            const BatchGroup* g = have ? &groups[i] : nullptr;
+            if (launch->h_group_ms) {
+                float ms = 0.0f;
+                if (have && timed) PILA_HIP(hipEventElapsedTime(&ms, t_ev[2 * i], t_ev[2 * i + 1]));
+                launch->h_group_ms[i] = ms;
+            }
+            if (launch->h_group_desc)
+                launch->h_group_desc[i] =
+                    have ? (g->kind & 255) | (g->shape ? (g->shape->cpw << 8) | (g->shape->e << 16) : 0) : 0;
+            if (launch->h_group_chains) launch->h_group_chains[i] = have ? (int)g->ids.size() : 0;
+        }
     }
     return PILA_OK;
 }

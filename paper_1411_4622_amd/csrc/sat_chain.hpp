@@ -642,6 +642,7 @@ __device__ inline void write_stats(const ChainJob& J, const ChainState& cs)
         st.chain_launches = 0;
         st.body = 0;
         st.chain_kernel_ms = 0.0;
+        st.t_begin = st.t_end = 0;
         *J.stats = st;
     }
     __syncthreads();

@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
         __syncthreads();
         const ChainJob J = uniform_job(*(const ChainJob*)desc);
         const bool cancelled = __builtin_amdgcn_readfirstlane(flags_s[0]) != 0;
+        const int64_t t0 = (int64_t)wall_clock64();
         if (!cancelled) {
             if constexpr (BODY == kPiped)
                 run_chain_piped<float, false, CPW, E, true, true>(J, lds, sh, false);
@@ -156,6 +157,8 @@ __global__ __launch_bounds__(kPipedThreads) void srv_ring_kernel(RingCtl* ctl, R
             } else {
                 st = *J.stats;
             }
+            st.t_begin = t0;
+            st.t_end = (int64_t)wall_clock64();
             const uint64_t* s64 = (const uint64_t*)&st;
             uint64_t* d64 = (uint64_t*)&sl->stats;
             for (int i = 0; i < (int)(sizeof(sat_stats) / 8); ++i)

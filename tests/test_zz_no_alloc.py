@@ -48,4 +48,4 @@ def test_static_matches_sat_run_twice(P):
     small = _slice(24, 30, 35, seed=6, masked=True, I0=1e4)
     prm = P.SatParams(n_steps=4000, seed=8, chain_id=2, m_cand=4, T0=None, q_auto=30, n_stages=20)
     st = _run_both(P, small, prm, "f64")
-    assert st["body"] == P._binding.BODY_PIPED
+    assert st["body"] & 0xff == P._binding.BODY_PIPED
