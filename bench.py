@@ -205,7 +205,7 @@ def run_c3(args) -> int:
     import datagen
     import paper_1411_4622_amd as P
     from bench_workloads import _params
-    from paper_1411_4622_amd.tune import tune_batch
+    from paper_1411_4622_amd import tune
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda", 0)
@@ -236,16 +236,35 @@ def run_c3(args) -> int:
     steps_total = sum(p.n_steps for p in params)
     key_of = [(sl.N, sl.U) for sl in slices]
 
-    def jobs_for(pl, dtype="f32", prm=None):
-        return [P.Job(pl[key_of[c]], sinos[c], imgs[c], (prm or params)[c]) for c in range(n)]
+    waves_of = [0] * n
 
-    for c in range(n):
-        imgs[c].copy_(f0s[c])
-    (waves, per_cu), table = tune_batch(jobs_for(pilas), sample_steps=4096)
-    log("c3: launch shape %d waves/chain, %d chains/CU (tuned: %s)"
-        % (waves, per_cu, ", ".join("(%d,%d) %.3g/s" % (r["waves_per_chain"], r["chains_per_cu"],
-                                                       r["proposals_per_s"]) for r in table)))
-    del pilas
+    def jobs_for(pl, prm=None, widths=None):
+        return [P.Job(pl[key_of[c]], sinos[c], imgs[c], (prm or params)[c], (widths or waves_of)[c])
+                for c in range(n)]
+
+    # launch shape: each geometry's workgroup width from the stored tuning
+    # table, or tuned now on 4096-step prefixes of the same chains
+    info = P.device_info()
+    jobs0 = jobs_for(pilas)
+    stored = None if args.retune else tune.load_table(info["name"])
+    per_cu = 1
+    if stored and tune.apply_table(jobs0, stored):
+        per_cu = int(stored["chains_per_cu"])
+        tuning = {"source": "stored table (paper_1411_4622_amd/tuned_launch.json)",
+                  "geometries": stored["geometries"]}
+    else:
+        for c in range(n):
+            imgs[c].copy_(f0s[c])
+        res = tune.tune_geometries(jobs0, waves=(8, 4), chains_per_cu=per_cu, sample_steps=4096)
+        tune.apply_table(jobs0, {"geometries": res})
+        tuning = {"source": "tuned in this run", "geometries": res}
+        if args.tune_out:
+            tune.save_table(res, info["name"], per_cu, 4096, args.tune_out)
+    waves_of = [j.waves_per_chain for j in jobs0]
+    waves = 8  # the launch default (every job carries its own width)
+    log("c3: widths per geometry (%s): %s" % (tuning["source"], ", ".join(
+        "%s -> %d" % (k, v["waves_per_chain"]) for k, v in sorted(tuning["geometries"].items()))))
+    del pilas, jobs0
 
     def one_step():
         pl = {k: P.pila_build(geoms[k]) for k in keys}
@@ -280,7 +299,6 @@ def run_c3(args) -> int:
 
     # per-slice latency inside the batch: device clock from the batch's first
     # chain start to each chain's end
-    info = P.device_info()
     rate = info["wallclock_khz"] * 1e3
     t_first = min(s["t_begin"] for s in st)
     lat_slice = np.array([(s["t_end"] - t_first) / rate for s in st])
@@ -319,7 +337,8 @@ def run_c3(args) -> int:
         prm64 = [_params(P, cfg, params[c].n_steps, cfg["chain_seed0"] + c, c, "f64") for c in range(n)]
         for c in range(n):
             imgs[c].copy_(f0s[c])
-        P.sat_run_batch(jobs_for(pl64, prm=prm64), waves_per_chain=8, chains_per_cu=1, stats=False)
+        P.sat_run_batch(jobs_for(pl64, prm=prm64, widths=[8] * n), waves_per_chain=8, chains_per_cu=1,
+                        stats=False)
         torch.cuda.synchronize()
         rm64 = [datagen.rmse(imgs[c].cpu().numpy(), slices[c].truth) for c in range(n)]
         del pl64
@@ -367,13 +386,14 @@ def run_c3(args) -> int:
     body_of = [s["body"] for s in st]
     acc = [s["accepts"] for s in st]
     b_chain = [chain_bytes(params[c].n_steps, M, fmean[key_of[c]], acc[c]) for c in range(n)]
-    gdesc = [(g["kind"], g["cpw"], g["e"]) for g in group_runs[-1]]
-    g_ms = {d: statistics.mean(next(g["ms"] for g in run if (g["kind"], g["cpw"], g["e"]) == d)
+    gdesc = [(g["kind"], g["cpw"], g["e"], g["waves"]) for g in group_runs[-1]]
+    g_ms = {d: statistics.mean(next(g["ms"] for g in run if (g["kind"], g["cpw"], g["e"], g["waves"]) == d)
                                 for run in group_runs) for d in gdesc}
     dom = max(g_ms, key=g_ms.get)
 
     def in_group(body, d):
-        return (body & 15) == d[0] and ((body >> 8) & 255) == d[1] and ((body >> 16) & 255) == d[2]
+        return ((body & 15) == d[0] and ((body >> 8) & 255) == d[1] and ((body >> 16) & 255) == d[2]
+                and ((body >> 24) & 255) == d[3])
 
     dom_chains = [c for c in range(n) if in_group(body_of[c], dom)]
     dom_bytes = sum(b_chain[c] for c in dom_chains)
@@ -426,8 +446,7 @@ def run_c3(args) -> int:
                               "lone_us_per_step": {"%dx%d" % k: v for k, v in sorted(lone_us.items())},
                               "how": "the same chains one at a time with sat_run, each geometry's "
                                      "per-step time from its first 100k steps"},
-        "launch": {"waves_per_chain": waves, "chains_per_cu": per_cu, "tuner": table,
-                   "groups": group_runs[-1]},
+        "launch": {"chains_per_cu": per_cu, "tuning": tuning, "groups": group_runs[-1]},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": g_ms[dom], "algorithmic_bytes_per_launch": dom_bytes,
@@ -453,6 +472,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-sanity", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="c3: tune the workgroup width per geometry even when a stored table exists")
+    ap.add_argument("--tune-out", default=None,
+                    help="c3: write the tuning results to this JSON file (when tuning)")
     ap.add_argument("--chain-steps", type=int, default=None,
                     help="c2: override the chain length (profiling runs); the reported config says so")
     ap.add_argument("--cpu-steps", type=int, default=1_000_000, help="c2: oracle steps timed")

@@ -51,6 +51,8 @@ extern "C" {
 /* storage / arithmetic types */
 #define PILA_F64 0
 #define PILA_F32 1
+#define PILA_U8 2  /* lengths only: one byte per length, round(180 l) (section II-B), read as
+                      the float q / 180; chains take it with an FP32 or an FP64 residual */
 
 /* cooling schedules (sat_params.schedule), section II-A and III-C */
 #define PILA_SCHED_LINEAR 0 /* Eq. 2:  T_n = T0 - n (T0 - TN) / N */
@@ -65,7 +67,7 @@ extern "C" {
 
 /* which chain body ran a chain (sat_stats.body): a kind plus flags, and for the
  * pipelined body its register shape: estimates per wavefront << 8 | row
- * entries per lane << 16 */
+ * entries per lane << 16; in a batch also its wavefronts per chain << 24 */
 #define PILA_BODY_PIPED 1     /* rows in registers, estimates drawn ahead */
 #define PILA_BODY_LONG 2      /* rows of more than 512 entries, one estimate per wavefront */
 #define PILA_BODY_GENERAL 3   /* any row length and M, draws at the step (needed for redraw) */
@@ -80,7 +82,7 @@ typedef struct pila_geom {
     int32_t n;                /* image side N (N x N unit pixels), >= 1 */
     int32_t n_angles;         /* U, >= 1 */
     int32_t n_bins;           /* K, detector bins at unit spacing, >= 1 */
-    int32_t len_dtype;        /* PILA_F64 or PILA_F32: storage type of lengths */
+    int32_t len_dtype;        /* PILA_F64, PILA_F32 or PILA_U8: storage type of lengths */
     const double* angles_deg; /* host [U], finite */
     const uint8_t* mask;      /* host [N*N], nonzero = support pixel; NULL = all */
 } pila_geom;
@@ -89,7 +91,7 @@ typedef struct pila_geom {
  * A built PILA.  All arrays are caller-allocated device memory.
  *   row_ptr [N*N+1]  pixel-major CSR offsets (int64)
  *   col     [nnz]    ray index g = u*K + k, strictly ascending within a row
- *   len     [nnz]    intersection length (double or float per len_dtype)
+ *   len     [nnz]    intersection length (double, float or byte per len_dtype)
  *   support [n_support] support pixel indices, ascending
  *   trig    [2*U]    (cos, sin) of every angle, as used for the build
  *   t_row_ptr [U*K+1], t_col [nnz], t_len [nnz]: the same entries ray-major
@@ -226,9 +228,10 @@ int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size
  *   change Delta C <= 0 or N1 < exp(-Delta C / T) (Step 4; N1 from counter
  *   (s, 0, 1, 0)); T from Eq. 2 at stage floor(s * n_stages / n_steps);
  *   on acceptance the residual is updated over the row (Eq. 6).
- * precision PILA_F64 needs len_dtype PILA_F64; PILA_F32 needs PILA_F32
- * (then the residual and the row sums are FP32, the cost total FP64, and the
- * residual is recomputed in FP64 every resync_every nonzero accepts).
+ * precision PILA_F64 needs len_dtype PILA_F64 or PILA_U8; PILA_F32 needs
+ * PILA_F32 or PILA_U8 (then the residual and the row sums are FP32, the cost
+ * total FP64, and the residual is recomputed in FP64 every resync_every
+ * nonzero accepts).  One-byte lengths enter every sum as q / 180.
  * h_stats (nullable) receives the chain's statistics: the call then
  * synchronises.  trace (nullable, host struct of device arrays) records
  * every step.  Errors: EINVAL (bad sizes/params, dtype mismatch, empty
@@ -266,6 +269,10 @@ typedef struct sat_job {
     const double* d_sino;
     double* d_image;
     sat_params params;
+    int32_t waves_per_chain; /* this chain's workgroup width (1, 2, 4, 8 or 16
+                                wavefronts; 0 = the launch's), e.g. from a tuning
+                                table per geometry */
+    int32_t reserved;
 } sat_job;
 
 /* Launch shape of the batched kernel (nullable: library default). */
@@ -277,8 +284,9 @@ typedef struct sat_launch {
     /* out, per group of chains that one persistent kernel runs (unused
      * entries get desc 0): the kernel's duration from HIP events recorded
      * around it on its stream, its body (PILA_BODY_* kind | register shape:
-     * estimates per wavefront << 8 | row entries per lane << 16) and its chain
-     * count.  Host arrays; filled when the call returns. */
+     * estimates per wavefront << 8 | row entries per lane << 16 | wavefronts
+     * per chain << 24) and its chain count.  Host arrays; filled when the
+     * call returns. */
     float* h_group_ms;
     int32_t* h_group_desc;
     int32_t* h_group_chains;
@@ -302,6 +310,58 @@ typedef struct sat_launch {
 int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs, size_t* bytes);
 int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch, void* d_ws,
                       size_t ws_bytes, sat_stats* h_stats, void* stream);
+
+/*
+ * HIP graphs of chains (section II-A Steps 1-4 per chain, as sat_run and
+ * sat_run_batch compute them).  A chain run alone enqueues one launch per
+ * FP32 resync segment plus the grid-wide rebuilds between them (thousands of
+ * launches for a long chain); a graph captures that sequence once and
+ * replays it with one launch.
+ *
+ * sat_graph_create captures what sat_run would enqueue for these arguments
+ * (no statistics, no kernel timing); sat_batch_graph_create what
+ * sat_run_batch would enqueue for these jobs: the descriptors are uploaded
+ * to d_ws once, synchronously, at creation, and the graph holds the ticket
+ * reset, the slot words and every group's persistent kernel with the
+ * fork/join dependencies between their streams.  Every pointer and size is
+ * fixed at creation: each launch re-runs the chains from whatever the images
+ * hold (callers copy the starting images in before a launch), with the
+ * same buffers, and gives the bits sat_run / sat_run_batch would give.
+ * sat_graph_launch enqueues one replay on a stream (asynchronous);
+ * sat_graph_stats copies the statistics of the last replay (one per chain,
+ * h_stats [chains]) and synchronises the stream; sat_graph_destroy frees
+ * the graph (NULL accepted).  The library allocates no device memory for
+ * a graph.  Errors: as sat_run / sat_run_batch, EHIP for capture failures.
+ */
+typedef struct sat_graph_s sat_graph;
+int32_t sat_graph_create(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                         const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                         const sat_trace* trace, sat_graph** out);
+int32_t sat_batch_graph_create(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch, void* d_ws,
+                               size_t ws_bytes, sat_graph** out);
+int32_t sat_graph_launch(sat_graph* g, void* stream);
+int32_t sat_graph_stats(sat_graph* g, sat_stats* h_stats, void* stream);
+int32_t sat_graph_destroy(sat_graph* g);
+
+/*
+ * sat_drt_run - the comparison method of section III-A: the SAT chain of
+ * sat_run (same estimates, temperatures, BoME choice and acceptance
+ * uniforms, Philox counters (s, m, 0, 0) and (s, 0, 1, 0)) whose evaluation
+ * step, instead of the PILA, projects each estimate's whole image by the
+ * discrete Radon transform with bilinear interpolation (ray (u, k) sampled
+ * at unit steps t = -T .. T, T = ceil(N / sqrt 2) + 1, at the points
+ * (s_k cos - t sin, s_k sin + t cos), the image interpolated bilinearly
+ * between pixel centres and zero outside) and takes its cost C' from Eq. 4;
+ * Delta C = C' - C.  It needs no PILA and is here to measure what the PILA
+ * saves (the paper reports over 300x on its CPU).  T0 and TN must be given.
+ * d_image in: start, out: result.  h_cost_final (nullable) receives Eq. 4
+ * of the final image; trace (nullable) records every step.  Synchronises
+ * the stream.  Errors: EINVAL (sizes, T0/TN not given, params), ENOMEM
+ * (workspace of sat_drt_workspace_size), EHIP.
+ */
+int32_t sat_drt_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes);
+int32_t sat_drt_run(const pila_geom* geom, const double* d_sino, const sat_params* params, double* d_image,
+                    void* d_ws, size_t ws_bytes, double* h_cost_final, const sat_trace* trace, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* SIRT with exact lengths (section III-D, Eq. 10-11)                        */
@@ -337,6 +397,35 @@ int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params* params, si
 int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
                  const sirt_params* params, double* d_image, void* d_ws, size_t ws_bytes,
                  double* h_cost, void* stream);
+
+/*
+ * sirt_seq_run - SIRT with exact lengths pixel by pixel, as section III-D
+ * describes it: the factor matrix W and the calculated projections Pc = A f
+ * are computed once; then n_iter times, m_per times, a support pixel p is
+ * chosen (Philox4x64-10, key (seed, 0), counter (n * m_per + m, 0, 3, 0),
+ * uniform over the support), moves by (lambda / U) * sum over its PILA row
+ * of l * (Pm_g - Pc_g) / W_g (Eq. 10-11 summed over all rays that cross the
+ * pixel, rays with W_g = 0 adding nothing), and its rays get Pc_g += change
+ * * l (Eq. 6).  d_image (N*N) in: start, out: result.  h_cost (nullable,
+ * n_iter doubles) receives Eq. 4 of the running projections after each
+ * iteration; the call then synchronises.  One wavefront runs the sequence
+ * (each update reads the projections the previous one wrote).  Row sums
+ * are added in a fixed order that differs from a row walk: results match
+ * the plain definition to rounding.  Errors: EINVAL (sizes, NULL arrays,
+ * non-finite lambda, empty support), ENOMEM (workspace), EHIP.
+ */
+typedef struct sirt_seq_params {
+    int32_t n_iter;    /* N: iterations */
+    int32_t reserved;
+    int64_t m_per;     /* M: pixel updates per iteration */
+    double lambda;     /* relaxation; 1 is the formula as printed */
+    uint64_t seed;     /* Philox key word 0 of the pixel choice */
+} sirt_seq_params;
+
+int32_t sirt_seq_workspace_size(const pila_geom* geom, const sirt_seq_params* params, size_t* bytes);
+int32_t sirt_seq_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                     const sirt_seq_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                     double* h_cost, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Serving: many independent chains (one slice each, section II-A Steps 1-4  */

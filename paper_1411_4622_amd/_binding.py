@@ -19,14 +19,16 @@ LIB_PATH = os.path.join(_HERE, "libpila.so")
 
 PILA_OK, PILA_EINVAL, PILA_ENOMEM, PILA_EHIP, PILA_ESIZE = 0, -1, -2, -3, -4
 PILA_ECANCELED, PILA_EBUSY, PILA_ENOTFOUND = -5, -6, -7
-PILA_F64, PILA_F32 = 0, 1
+PILA_F64, PILA_F32, PILA_U8 = 0, 1, 2
 SCHEDULES = {"linear": 0, "exp": 1, "cubic": 2}      # PILA_SCHED_*
 PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
 BODY_PIPED, BODY_LONG, BODY_GENERAL = 1, 2, 3         # PILA_BODY_* kinds
 BODY_GLOBAL_R, BODY_SEGMENTED = 16, 32                # PILA_BODY_* flags
 
 EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run", "sat_run_static",
-            "sat_batch_workspace_size", "sat_run_batch", "sirt_workspace_size", "sirt_run",
+            "sat_batch_workspace_size", "sat_run_batch", "sat_graph_create", "sat_batch_graph_create",
+            "sat_graph_launch", "sat_graph_stats", "sat_graph_destroy", "sirt_workspace_size", "sirt_run",
+            "sirt_seq_workspace_size", "sirt_seq_run", "sat_drt_workspace_size", "sat_drt_run",
             "srv_create", "srv_prepare", "srv_submit", "srv_poll", "srv_cancel", "srv_get_status",
             "srv_destroy", "pila_get_device_info", "pila_last_error"]
 
@@ -73,7 +75,8 @@ class CSatTrace(C.Structure):
 
 class CSatJob(C.Structure):
     _fields_ = [("geom", C.POINTER(CGeom)), ("csr", C.POINTER(CCsr)), ("d_sino", C.c_void_p),
-                ("d_image", C.c_void_p), ("params", CSatParams)]
+                ("d_image", C.c_void_p), ("params", CSatParams), ("waves_per_chain", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class CSatLaunch(C.Structure):
@@ -85,6 +88,11 @@ class CSatLaunch(C.Structure):
 
 class CSirtParams(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double)]
+
+
+class CSirtSeqParams(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("reserved", C.c_int32), ("m_per", C.c_int64), ("lam", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class CSrvConfig(C.Structure):
@@ -136,8 +144,19 @@ def load(path: str = LIB_PATH):
     lib.sat_batch_workspace_size.argtypes = [I32, C.POINTER(CSatJob), C.POINTER(C.c_size_t)]
     lib.sat_run_batch.argtypes = [I32, C.POINTER(CSatJob), C.POINTER(CSatLaunch), V, C.c_size_t,
                                   C.POINTER(CSatStats), V]
+    lib.sat_graph_create.argtypes = [G, CS, V, C.POINTER(CSatParams), V, V, C.c_size_t,
+                                     C.POINTER(CSatTrace), C.POINTER(V)]
+    lib.sat_batch_graph_create.argtypes = [I32, C.POINTER(CSatJob), C.POINTER(CSatLaunch), V, C.c_size_t,
+                                           C.POINTER(V)]
+    lib.sat_graph_launch.argtypes = [V, V]
+    lib.sat_graph_stats.argtypes = [V, C.POINTER(CSatStats), V]
+    lib.sat_graph_destroy.argtypes = [V]
     lib.sirt_workspace_size.argtypes = [G, C.POINTER(CSirtParams), C.POINTER(C.c_size_t)]
     lib.sirt_run.argtypes = [G, CS, V, C.POINTER(CSirtParams), V, V, C.c_size_t, V, V]
+    lib.sat_drt_workspace_size.argtypes = [G, C.POINTER(CSatParams), C.POINTER(C.c_size_t)]
+    lib.sat_drt_run.argtypes = [G, V, C.POINTER(CSatParams), V, V, C.c_size_t, V, C.POINTER(CSatTrace), V]
+    lib.sirt_seq_workspace_size.argtypes = [G, C.POINTER(CSirtSeqParams), C.POINTER(C.c_size_t)]
+    lib.sirt_seq_run.argtypes = [G, CS, V, C.POINTER(CSirtSeqParams), V, V, C.c_size_t, V, V]
     lib.srv_create.argtypes = [C.POINTER(CSrvConfig), C.POINTER(V)]
     lib.srv_prepare.argtypes = [V, G]
     lib.srv_submit.argtypes = [V, C.POINTER(CSrvRequest), C.POINTER(C.c_uint64)]
@@ -190,7 +209,9 @@ class Geometry:
         self.n_angles = len(self.angles)
         self.n_bins = int(n_bins)
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
-        self.len_dtype = PILA_F32 if len_dtype in ("f32", PILA_F32) else PILA_F64
+        self.len_dtype = {"f64": PILA_F64, "f32": PILA_F32, "u8": PILA_U8}.get(len_dtype, len_dtype)
+        if self.len_dtype not in (PILA_F64, PILA_F32, PILA_U8):
+            raise ValueError("len_dtype must be 'f64', 'f32' or 'u8'")
         self._c = CGeom(self.n, self.n_angles, self.n_bins, self.len_dtype,
                         self.angles.ctypes.data, None if self.mask is None else self.mask.ctypes.data)
 
@@ -248,7 +269,7 @@ def pila_build(geom: Geometry, device=None) -> Pila:
                           _stream()))
     nnz, P, max_row = int(csr.nnz), int(csr.n_support), int(csr.max_row)
     k_lo, k_hi = int(csr.k_lo), int(csr.k_hi)
-    ldt = torch.float64 if geom.len_dtype == PILA_F64 else torch.float32
+    ldt = {PILA_F64: torch.float64, PILA_F32: torch.float32, PILA_U8: torch.uint8}[geom.len_dtype]
     col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
     ln = torch.empty(max(nnz, 1), dtype=ldt, device=dev)
     t_col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
@@ -391,6 +412,7 @@ class Job:
     sino: object
     image: object
     params: SatParams
+    waves_per_chain: int = 0        # 0: the batch's launch shape
 
 
 MAX_GROUPS = 8
@@ -414,6 +436,7 @@ def sat_run_batch(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: int 
         cj[i].d_sino = j.sino.data_ptr()
         cj[i].d_image = j.image.data_ptr()
         cj[i].params = j.params.c()
+        cj[i].waves_per_chain = j.waves_per_chain
         keep.append(j)
     lib = load()
     nb = C.c_size_t(0)
@@ -437,8 +460,81 @@ def sat_run_batch(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: int 
             d = int(g_desc[i])
             if d:
                 groups.append(dict(ms=float(g_ms[i]), kind=d & 255, cpw=(d >> 8) & 255,
-                                   e=(d >> 16) & 255, chains=int(g_n[i])))
+                                   e=(d >> 16) & 255, waves=(d >> 24) & 255, chains=int(g_n[i])))
     return [_stats_dict(st[i]) for i in range(n)] if stats else None
+
+
+class Graph:
+    """A chain's or a batch's launches captured once in a HIP graph
+    (sat_graph_* ABI).  launch() replays it on torch's current stream; the
+    buffers it was made with (images, sinograms, PILAs, workspace) are kept
+    alive here and must not be reallocated; copy starting images into them
+    before a launch.  stats() returns the last replay's statistics."""
+
+    def __init__(self, handle, n_chains: int, keep):
+        self._h = handle
+        self.n_chains = n_chains
+        self._keep = keep
+
+    def launch(self):
+        _check(load().sat_graph_launch(self._h, _stream()))
+
+    def stats(self) -> List[dict]:
+        st = (CSatStats * self.n_chains)()
+        _check(load().sat_graph_stats(self._h, st, _stream()))
+        return [_stats_dict(st[i]) for i in range(self.n_chains)]
+
+    def close(self):
+        if self._h:
+            _check(load().sat_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sat_graph(pila: Pila, sino, params: SatParams, image, workspace=None, trace=None) -> Graph:
+    """Capture sat_run's launches for these buffers into a graph."""
+    torch = _torch()
+    g = pila.geom
+    assert image.dtype == torch.float64 and image.is_cuda and image.is_contiguous()
+    ws = workspace if workspace is not None else sat_workspace(g, params, image.device)
+    p = params.c()
+    ctr = None
+    if trace is not None:
+        ctr = CSatTrace(trace["m_star"].data_ptr(), trace["accept"].data_ptr(), trace["dC"].data_ptr())
+    h = C.c_void_p()
+    _check(load().sat_graph_create(C.byref(g.c), C.byref(pila.c), sino.data_ptr(), C.byref(p),
+                                   image.data_ptr(), ws.data_ptr(), ws.numel(),
+                                   C.byref(ctr) if ctr is not None else None, C.byref(h)))
+    return Graph(h, 1, (pila, sino, image, ws, trace))
+
+
+def sat_batch_graph(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: int = 2,
+                    lds_residual: bool = True, workspace=None) -> Graph:
+    """Capture sat_run_batch's launches for these jobs into a graph."""
+    torch = _torch()
+    n = len(jobs)
+    cj = (CSatJob * max(n, 1))()
+    for i, j in enumerate(jobs):
+        cj[i].geom = C.pointer(j.pila.geom.c)
+        cj[i].csr = C.pointer(j.pila.c)
+        cj[i].d_sino = j.sino.data_ptr()
+        cj[i].d_image = j.image.data_ptr()
+        cj[i].params = j.params.c()
+        cj[i].waves_per_chain = j.waves_per_chain
+    lib = load()
+    nb = C.c_size_t(0)
+    _check(lib.sat_batch_workspace_size(n, cj, C.byref(nb)))
+    ws = workspace if workspace is not None else torch.empty(int(nb.value), dtype=torch.uint8,
+                                                             device="cuda")
+    launch = CSatLaunch(waves_per_chain, chains_per_cu, 1 if lds_residual else 0, 0)
+    h = C.c_void_p()
+    _check(lib.sat_batch_graph_create(n, cj, C.byref(launch), ws.data_ptr(), ws.numel(), C.byref(h)))
+    return Graph(h, n, (list(jobs), ws))
 
 
 def sirt_run(pila: Pila, sino, n_iter: int, lam: float, image, workspace=None,
@@ -458,6 +554,52 @@ def sirt_run(pila: Pila, sino, n_iter: int, lam: float, image, workspace=None,
     _check(lib.sirt_run(C.byref(g.c), C.byref(pila.c), sino.data_ptr(), C.byref(p), image.data_ptr(),
                         workspace.data_ptr(), workspace.numel(),
                         costs.ctypes.data if costs is not None else None, _stream()))
+    return costs[:n_iter] if costs is not None else None
+
+
+def sat_drt_run(geom: Geometry, sino, params: SatParams, image, trace: bool = False):
+    """SAT with the bilinear DRT in the evaluation step (section III-A's
+    comparison method).  Returns (final cost, trace dict of device tensors or
+    None); image updated in place."""
+    torch = _torch()
+    assert image.dtype == torch.float64 and image.is_cuda and image.is_contiguous()
+    assert sino.dtype == torch.float64 and sino.is_cuda and sino.is_contiguous()
+    p = params.c()
+    lib = load()
+    nb = C.c_size_t(0)
+    _check(lib.sat_drt_workspace_size(C.byref(geom.c), C.byref(p), C.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=image.device)
+    tr = ctr = None
+    if trace:
+        n = params.n_steps
+        tr = dict(m_star=torch.empty(n, dtype=torch.int32, device=image.device),
+                  accept=torch.empty(n, dtype=torch.uint8, device=image.device),
+                  dC=torch.empty(n, dtype=torch.float64, device=image.device))
+        ctr = CSatTrace(tr["m_star"].data_ptr(), tr["accept"].data_ptr(), tr["dC"].data_ptr())
+    c = C.c_double(0.0)
+    _check(lib.sat_drt_run(C.byref(geom.c), sino.data_ptr(), C.byref(p), image.data_ptr(), ws.data_ptr(),
+                           ws.numel(), C.byref(c), C.byref(ctr) if ctr is not None else None, _stream()))
+    return float(c.value), tr
+
+
+def sirt_seq_run(pila: Pila, sino, n_iter: int, m_per: int, lam: float, image, seed: int = 0,
+                 workspace=None, cost: bool = True):
+    """Pixel-by-pixel SIRT (section III-D as described); image updated in
+    place; returns Eq. 4 after each iteration."""
+    torch = _torch()
+    g = pila.geom
+    assert image.dtype == torch.float64 and image.is_cuda and image.is_contiguous()
+    assert sino.dtype == torch.float64 and sino.is_cuda and sino.is_contiguous()
+    p = CSirtSeqParams(int(n_iter), 0, int(m_per), float(lam), int(seed))
+    lib = load()
+    if workspace is None:
+        nb = C.c_size_t(0)
+        _check(lib.sirt_seq_workspace_size(C.byref(g.c), C.byref(p), C.byref(nb)))
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=image.device)
+    costs = np.zeros(max(n_iter, 1), dtype=np.float64) if cost else None
+    _check(lib.sirt_seq_run(C.byref(g.c), C.byref(pila.c), sino.data_ptr(), C.byref(p), image.data_ptr(),
+                            workspace.data_ptr(), workspace.numel(),
+                            costs.ctypes.data if costs is not None else None, _stream()))
     return costs[:n_iter] if costs is not None else None
 
 

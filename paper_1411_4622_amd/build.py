@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpila.so")
-SOURCES = ["abi.hip", "pila_build.hip", "project.hip", "sat.hip", "server.hip"]
+SOURCES = ["abi.hip", "pila_build.hip", "project.hip", "sat.hip", "server.hip", "sirt_seq.hip", "drt.hip"]
 ARCH = os.environ.get("PILA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -50,8 +50,8 @@ int32_t check_geom(const pila_geom* g)
         return fail(PILA_EINVAL, "bad sizes n=%d U=%d K=%d", g->n, g->n_angles, g->n_bins);
     if ((int64_t)g->n * g->n > (int64_t)1 << 30 || (int64_t)g->n_angles * g->n_bins > (int64_t)1 << 30)
         return fail(PILA_EINVAL, "geometry too large (n=%d U=%d K=%d)", g->n, g->n_angles, g->n_bins);
-    if (g->len_dtype != PILA_F64 && g->len_dtype != PILA_F32)
-        return fail(PILA_EINVAL, "len_dtype must be PILA_F64 or PILA_F32 (got %d)", g->len_dtype);
+    if (g->len_dtype != PILA_F64 && g->len_dtype != PILA_F32 && g->len_dtype != PILA_U8)
+        return fail(PILA_EINVAL, "len_dtype must be PILA_F64, PILA_F32 or PILA_U8 (got %d)", g->len_dtype);
     if (!g->angles_deg) return fail(PILA_EINVAL, "angles_deg is NULL");
     for (int u = 0; u < g->n_angles; ++u)
         if (!std::isfinite(g->angles_deg[u]))

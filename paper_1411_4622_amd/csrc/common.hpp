@@ -31,10 +31,32 @@ void clear_error();
 constexpr double kTau = 1e-9;  // lengths at or below this (corner touches) are not stored
 constexpr int kWave = 64;
 
+// One-byte intersection length (section II-B: the length times 180,
+// rounded; halves away from zero).  It stands for the float q / 180,
+// correctly rounded, which for every byte value equals q * fl(1/180) with
+// one fused multiply-add correction of its residual (three instructions
+// instead of a division; the identity is checked exhaustively by the test
+// suite).  Kernels templated on the length type read it through this float
+// conversion; the PILA build stores it through the constructor.
+struct LenQ {
+    uint8_t q;
+    LenQ() = default;
+    __host__ __device__ explicit LenQ(double l) : q((uint8_t)round(180.0 * l)) {}
+    __host__ __device__ operator float() const
+    {
+        const float x = (float)q, c = 1.0f / 180.0f;
+        const float r = x * c;
+        return fmaf(fmaf(-r, 180.0f, x), c, r);
+    }
+};
+static_assert(sizeof(LenQ) == 1, "one byte per length");
+
 // host: (cos, sin) of degrees, exact at multiples of 90 degrees
 void trig_of(double deg, double* c, double* s);
 // host: validate a geometry (sizes, finite angles, dtype)
 int32_t check_geom(const pila_geom* g);
+// host: bytes of one stored length of a len_dtype
+inline int len_bytes(int32_t dtype) { return dtype == PILA_F64 ? 8 : dtype == PILA_F32 ? 4 : 1; }
 
 // ---------------------------------------------------------------------------
 // device: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11)

@@ -347,8 +347,10 @@ int32_t pila::pila_build_with(const pila_geom* geom, pila_csr* csr, void* d_scra
                     support.size());
     if (geom->len_dtype == PILA_F64)
         launch_fill<double>(geom, csr, mk, st);
-    else
+    else if (geom->len_dtype == PILA_F32)
         launch_fill<float>(geom, csr, mk, st);
+    else
+        launch_fill<LenQ>(geom, csr, mk, st);
     PILA_HIP(hipGetLastError());
     if (!support.empty())
         PILA_HIP(hipMemcpyAsync(csr->support, support.data(), sizeof(int32_t) * support.size(),

@@ -731,7 +731,7 @@ struct SirtLayout {
 SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
 {
     const size_t G = (size_t)g->n_angles * g->n_bins, NP = (size_t)g->n * g->n;
-    const size_t ls = g->len_dtype == PILA_F32 ? 4 : 8;
+    const size_t ls = (size_t)len_bytes(g->len_dtype);
     const size_t cells = n_tiles * (size_t)g->n_angles * 64;
     SirtLayout L;
     size_t at = 0;
@@ -801,9 +801,12 @@ extern "C" int32_t pila_forward(const pila_geom* geom, const pila_csr* csr, cons
     if (geom->len_dtype == PILA_F64)
         ray_gather_kernel<double, kFwd><<<gather_blocks(G), 256, 0, st>>>(
             G, csr->t_row_ptr, csr->t_col, (const double*)csr->t_len, d_image, nullptr, nullptr, d_out, nullptr);
-    else
+    else if (geom->len_dtype == PILA_F32)
         ray_gather_kernel<float, kFwd><<<gather_blocks(G), 256, 0, st>>>(
             G, csr->t_row_ptr, csr->t_col, (const float*)csr->t_len, d_image, nullptr, nullptr, d_out, nullptr);
+    else
+        ray_gather_kernel<LenQ, kFwd><<<gather_blocks(G), 256, 0, st>>>(
+            G, csr->t_row_ptr, csr->t_col, (const LenQ*)csr->t_len, d_image, nullptr, nullptr, d_out, nullptr);
     PILA_HIP(hipGetLastError());
     return PILA_OK;
 }
@@ -819,9 +822,12 @@ extern "C" int32_t pila_backproject(const pila_geom* geom, const pila_csr* csr, 
     if (geom->len_dtype == PILA_F64)
         pixel_gather_kernel<double, kBack><<<gather_blocks(NP), 256, 0, st>>>(
             NP, csr->row_ptr, csr->col, (const double*)csr->len, d_sino, d_out, 0.0);
-    else
+    else if (geom->len_dtype == PILA_F32)
         pixel_gather_kernel<float, kBack><<<gather_blocks(NP), 256, 0, st>>>(
             NP, csr->row_ptr, csr->col, (const float*)csr->len, d_sino, d_out, 0.0);
+    else
+        pixel_gather_kernel<LenQ, kBack><<<gather_blocks(NP), 256, 0, st>>>(
+            NP, csr->row_ptr, csr->col, (const LenQ*)csr->len, d_sino, d_out, 0.0);
     PILA_HIP(hipGetLastError());
     return PILA_OK;
 }
@@ -932,5 +938,7 @@ extern "C" int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const do
     hipStream_t st = (hipStream_t)stream;
     if (geom->len_dtype == PILA_F64)
         return sirt_impl<double>(geom, csr, d_sino, params, d_image, (char*)d_ws, h_cost, st);
-    return sirt_impl<float>(geom, csr, d_sino, params, d_image, (char*)d_ws, h_cost, st);
+    if (geom->len_dtype == PILA_F32)
+        return sirt_impl<float>(geom, csr, d_sino, params, d_image, (char*)d_ws, h_cost, st);
+    return sirt_impl<LenQ>(geom, csr, d_sino, params, d_image, (char*)d_ws, h_cost, st);
 }

@@ -3,6 +3,7 @@
 // algorithm are in sat_chain.hpp.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -42,8 +43,8 @@ int32_t check_params(const pila_geom* g, const pila_csr* c, const sat_params* p)
     if (p->n_steps < 0 || p->n_stages < 1) return fail(PILA_EINVAL, "bad n_steps / n_stages");
     if (p->precision != PILA_F64 && p->precision != PILA_F32)
         return fail(PILA_EINVAL, "precision must be PILA_F64 or PILA_F32");
-    if (p->precision != g->len_dtype)
-        return fail(PILA_EINVAL, "the residual precision must match the PILA length type");
+    if (g->len_dtype != PILA_U8 && p->precision != g->len_dtype)
+        return fail(PILA_EINVAL, "the residual precision must match the PILA length type (or the lengths be one byte)");
     if (!(p->T0 > 0.0) && (p->q_auto < 1 || !(p->tn_ratio > 0.0)))
         return fail(PILA_EINVAL, "automatic T0 needs q_auto >= 1 and tn_ratio > 0");
     if (p->T0 > 0.0 && !(p->TN > 0.0 && std::isfinite(p->T0) && std::isfinite(p->TN)))
@@ -111,7 +112,7 @@ ChainJob make_job(const pila_geom* g, const pila_csr* c, const double* sino, con
         J.kdiv_m = (uint32_t)((den + (uint64_t)J.K - 1) / (uint64_t)J.K);
     }
     J.rkb = (J.K + 7) / 8;
-    J.rpad = 0;
+    J.lenq = g->len_dtype == PILA_U8 ? 1 : 0;
     const size_t T = (G + 63) / 64;
     const size_t rb = align256(rs * residual_values(g));
     J.r = ws;
@@ -141,7 +142,7 @@ bool piped_allowed(const pila_geom* g, const pila_csr* c)
     // ray index g = u K + k below 2^24 (the multiply-shift split), bins
     // below 8192 (the patch-table tag), and 32-bit byte offsets into the rows
     const int64_t G = (int64_t)g->n_angles * g->n_bins;
-    const int64_t lb = g->len_dtype == PILA_F32 ? 4 : 8;
+    const int64_t lb = len_bytes(g->len_dtype);
     return c->nnz >= 1 && c->max_row >= 1 && g->n_bins < 8192 && G < (1 << 24) &&
            c->nnz * lb <= ((int64_t)1 << 32);
 }
@@ -185,22 +186,22 @@ int32_t set_lds(const void* k, int bytes)
 namespace {
 
 // one chain, pipelined body (rows in registers); TK: slot words from job.tcol
-template <typename Real, bool RLDS, int CPW, int E, bool TK = false>
+template <typename Real, bool RLDS, int CPW, int E, bool TK = false, typename LenT = Real>
 __global__ __launch_bounds__(kPipedThreads) void sat_piped_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_piped<Real, RLDS, CPW, E, false, TK>(job, lds, sh, false);
+    run_chain_piped<Real, RLDS, CPW, E, false, TK, LenT>(job, lds, sh, false);
 }
 
 // one segment of a chain whose FP64 resyncs run grid-wide between segments
-template <int CPW, int E, bool TK = false>
+template <int CPW, int E, bool TK = false, typename LenT = float>
 __global__ __launch_bounds__(kPipedThreads) void sat_segment_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_piped<float, false, CPW, E, false, TK>(job, lds, sh, true);
+    run_chain_piped<float, false, CPW, E, false, TK, LenT>(job, lds, sh, true);
 }
 
 // the slot word (ray_slot) of every PILA entry, for the TK kernels
@@ -212,46 +213,47 @@ __global__ __launch_bounds__(256) void tcol_kernel(ChainJob J, int64_t nnz, int3
 }
 
 // one chain, long-row body (64 E entries per row in registers, one estimate per wavefront)
-template <typename Real, bool RLDS, int E>
+template <typename Real, bool RLDS, int E, typename LenT = Real>
 __global__ __launch_bounds__(kPipedThreads) void sat_long_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_long<Real, RLDS, E>(job, lds, sh, false);
+    run_chain_long<Real, RLDS, E, false, LenT>(job, lds, sh, false);
 }
 
 // one segment of a long-row chain whose FP64 resyncs run grid-wide between segments
-template <int E>
+template <int E, typename LenT = float>
 __global__ __launch_bounds__(kPipedThreads) void sat_long_segment_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_long<float, false, E>(job, lds, sh, true);
+    run_chain_long<float, false, E, false, LenT>(job, lds, sh, true);
 }
 
 // one segment of a general-body chain (FP32, residual in global memory)
 // whose FP64 resyncs run grid-wide between segments
+template <typename LenT = float>
 __global__ __launch_bounds__(1024) void sat_simple_segment_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_simple<float, false>(job, lds, sh, true);
+    run_chain_simple<float, false, LenT>(job, lds, sh, true);
 }
 
 // one chain, general body
-template <typename Real>
+template <typename Real, typename LenT = Real>
 __global__ __launch_bounds__(1024) void sat_simple_kernel(ChainJob job, int lds_bytes)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_simple_dispatch<Real>(job, lds, lds_bytes, sh);
+    run_chain_simple_dispatch<Real, LenT>(job, lds, lds_bytes, sh);
 }
 
 // Grid-wide FP64 rebuild of a chain's residual, one wavefront per 64-ray
 // tile.  measure: a resync (runs only when the segment asked for one).
-template <typename Real>
+template <typename Real, typename LenT = Real>
 __global__ __launch_bounds__(256) void sat_rebuild_kernel(ChainJob job, int measure)
 {
     if (measure && !job.carry->resync_due) return;
@@ -259,11 +261,11 @@ __global__ __launch_bounds__(256) void sat_rebuild_kernel(ChainJob job, int meas
     const int G = job.U * job.K, T = (G + kWave - 1) / kWave;
     const int waves = gridDim.x * (blockDim.x >> 6);
     for (int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < T; t += waves)
-        rebuild_tile<Real, true>(job, (Real*)job.r, G, t, measure != 0, lane);
+        rebuild_tile<Real, true, LenT>(job, (Real*)job.r, G, t, measure != 0, lane);
 }
 
 // After the initial rebuild: sum of squares and Eq. 8, then the carry.
-template <typename Real>
+template <typename Real, typename LenT = Real>
 __global__ __launch_bounds__(512) void sat_setup_kernel(ChainJob job)
 {
     __shared__ ChainShared sh;
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(512) void sat_setup_kernel(ChainJob job)
     double T0 = job.T0, TN = job.TN;
     int32_t status = PILA_OK;
     if (!(T0 > 0.0))
-        auto_temperature<Real, true>(job, (const Real*)job.r, sse, sh, lane, wave, NW, &T0, &TN, &status);
+        auto_temperature<Real, true, LenT>(job, (const Real*)job.r, sse, sh, lane, wave, NW, &T0, &TN, &status);
     if (threadIdx.x == 0) {
         ChainCarry& c = *job.carry;
         c.s_next = 0;
@@ -353,7 +355,7 @@ __device__ __forceinline__ void stamp_chain(const ChainJob& J, int64_t t0)
     }
 }
 
-template <typename Real, int CPW, int E>
+template <typename Real, int CPW, int E, typename LenT = Real>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
     const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
     int* __restrict__ ticket, int lds_bytes)
@@ -369,13 +371,13 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
         if (j >= n_jobs) break;
         const int64_t t0 = (int64_t)wall_clock64();
         const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
-        run_chain_piped<Real, false, CPW, E, false, sizeof(Real) == 4>(J, lds, sh, false);
+        run_chain_piped<Real, false, CPW, E, false, sizeof(Real) == 4, LenT>(J, lds, sh, false);
         stamp_chain(J, t0);
     }
 }
 
 // Persistent batch of long-row chains (one estimate per wavefront)
-template <typename Real, int E>
+template <typename Real, int E, typename LenT = Real>
 __global__ __launch_bounds__(kPipedThreads) void sat_batch_long_kernel(
     const ChainJob* __restrict__ jobs, const int* __restrict__ order, int n_jobs,
     int* __restrict__ ticket, int lds_bytes)
@@ -391,13 +393,14 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_long_kernel(
         if (j >= n_jobs) break;
         const int64_t t0 = (int64_t)wall_clock64();
         const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
-        run_chain_long<Real, false, E>(J, lds, sh, false);
+        run_chain_long<Real, false, E, false, LenT>(J, lds, sh, false);
         stamp_chain(J, t0);
     }
 }
 
-// Persistent batch for the general body (any row length, M, precision or
-// proposal rule)
+// Persistent batch for the general body (any row length, M or proposal
+// rule), one kernel per residual precision and length type
+template <typename Real, typename LenT = Real>
 __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* __restrict__ jobs,
                                                                 const int* __restrict__ order,
                                                                 int n_jobs, int* __restrict__ ticket,
@@ -413,10 +416,7 @@ __global__ __launch_bounds__(1024) void sat_batch_simple_kernel(const ChainJob* 
         if (j >= n_jobs) break;
         const int64_t t0 = (int64_t)wall_clock64();
         const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
-        if (J.precision == PILA_F32)
-            run_chain_simple_dispatch<float>(J, lds, lds_bytes, sh);
-        else
-            run_chain_simple_dispatch<double>(J, lds, lds_bytes, sh);
+        run_chain_simple_dispatch<Real, LenT>(J, lds, lds_bytes, sh);
         stamp_chain(J, t0);
     }
 }
@@ -450,7 +450,21 @@ PipedShape piped_shape()
             seg_tk};
 }
 
-const std::vector<PipedShape>& piped_shapes(int precision)
+// one-byte lengths (FP32 only): the LDS-residual kernel and the global ones
+// with precomputed slot words
+template <int CPW, int E>
+PipedShape piped_shape_q()
+{
+    return {CPW,
+            E,
+            sat_piped_kernel<float, true, CPW, E, false, LenQ>,
+            nullptr,
+            nullptr,
+            sat_piped_kernel<float, false, CPW, E, true, LenQ>,
+            sat_segment_kernel<CPW, E, true, LenQ>};
+}
+
+const std::vector<PipedShape>& piped_shapes(int precision, bool lenq)
 {
     static const std::vector<PipedShape> f64 = {
         piped_shape<double, 1, 2>(), piped_shape<double, 1, 4>(), piped_shape<double, 2, 4>(),
@@ -458,18 +472,22 @@ const std::vector<PipedShape>& piped_shapes(int precision)
     static const std::vector<PipedShape> f32 = {
         piped_shape<float, 1, 4>(), piped_shape<float, 1, 8>(), piped_shape<float, 2, 8>(),
         piped_shape<float, 4, 8>()};
+    static const std::vector<PipedShape> q32 = {piped_shape_q<1, 4>(), piped_shape_q<1, 8>(),
+                                                piped_shape_q<2, 8>()};
+    static const std::vector<PipedShape> none;
+    if (lenq) return precision == PILA_F32 ? q32 : none;
     return precision == PILA_F64 ? f64 : f32;
 }
 
 // Pick the pipelined shape for one chain: the fewest estimates per
 // wavefront (most lanes per row) whose registers hold the longest row and
 // whose wavefront count fits the kernel.  Returns nullptr when none fits.
-const PipedShape* choose_piped(int precision, int m_cand, int max_row, int* waves)
+const PipedShape* choose_piped(int precision, bool lenq, int m_cand, int max_row, int* waves)
 {
     for (int cpw : {1, 2, 4}) {
         const int nw = (m_cand + cpw - 1) / cpw;
         if (nw * kWave > kPipedThreads) continue;
-        for (const PipedShape& ps : piped_shapes(precision)) {
+        for (const PipedShape& ps : piped_shapes(precision, lenq)) {
             if (ps.cpw != cpw || max_row > (kWave / cpw) * ps.e) continue;
             *waves = nw;
             return &ps;
@@ -487,13 +505,18 @@ struct BatchShape {
 
 // the pipelined shapes of the batch kernels, per precision (FP64 rows hold
 // at most 256 entries in registers; longer FP64 rows take the long-row body)
-const std::vector<BatchShape>& batch_shapes(int precision)
+const std::vector<BatchShape>& batch_shapes(int precision, bool lenq)
 {
     static const std::vector<BatchShape> f32 = {
         {1, 4, sat_batch_kernel<float, 1, 4>}, {1, 8, sat_batch_kernel<float, 1, 8>},
         {2, 8, sat_batch_kernel<float, 2, 8>}, {4, 8, sat_batch_kernel<float, 4, 8>}};
     static const std::vector<BatchShape> f64 = {{1, 4, sat_batch_kernel<double, 1, 4>},
                                                 {2, 8, sat_batch_kernel<double, 2, 8>}};
+    static const std::vector<BatchShape> q32 = {{1, 4, sat_batch_kernel<float, 1, 4, LenQ>},
+                                                {1, 8, sat_batch_kernel<float, 1, 8, LenQ>},
+                                                {2, 8, sat_batch_kernel<float, 2, 8, LenQ>}};
+    static const std::vector<BatchShape> none;
+    if (lenq) return precision == PILA_F32 ? q32 : none;
     return precision == PILA_F64 ? f64 : f32;
 }
 
@@ -581,7 +604,8 @@ extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* p
 // events around each chain-kernel launch (they are created per call).
 static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
                             const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
-                            sat_stats* h_stats, const sat_trace* trace, void* stream, bool timed)
+                            sat_stats* h_stats, const sat_trace* trace, void* stream, bool timed,
+                            int* body_out = nullptr)
 {
     PILA_TRY(check_params(geom, csr, params));
     if (!d_sino || !d_image) return fail(PILA_EINVAL, "sinogram or image is NULL");
@@ -607,18 +631,22 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
     int waves = 0;
     // redrawn proposals depend on the image value at the step: general body only
     const bool ahead = params->proposal == PILA_PROP_CLAMP;
+    const bool lenq = J.lenq != 0;
     const PipedShape* ps = ahead && piped_allowed(geom, csr)
-                               ? choose_piped(params->precision, params->m_cand, csr->max_row, &waves)
+                               ? choose_piped(params->precision, lenq, params->m_cand, csr->max_row, &waves)
                                : nullptr;
     const bool resync = params->precision == PILA_F32 && params->resync_every > 0;
-    // rows too long for the pipelined body's registers: the long-row body
-    const bool lng = ahead && !ps && long_allowed(geom, csr, params);
-    const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && ps->k_seg;
     // the pipelined body in global mode takes the entries' slot words
-    // precomputed when the workspace has room for them
+    // precomputed when the workspace has room for them (one-byte lengths:
+    // only then)
     const size_t tcb = align256((size_t)csr->nnz * sizeof(int32_t));
     const bool tk = ps && !r_in_lds && table_lds <= budget && ps->k_glob_tk && tcol_bytes(geom, params) > 0 &&
                     ws_bytes >= need + tcb;
+    if (ps && !r_in_lds && !tk && !ps->k_glob) ps = nullptr;
+    // rows too long for the pipelined body's registers: the long-row body
+    // (one-byte lengths: FP32 only)
+    const bool lng = ahead && !ps && long_allowed(geom, csr, params) && !(lenq && params->precision == PILA_F64);
+    const bool piped_seg = ps && !r_in_lds && table_lds <= budget && resync && (tk ? ps->k_seg_tk : ps->k_seg);
     if (tk) {
         J.tcol = (const int32_t*)((char*)d_ws + need);
         if (csr->nnz > 0)
@@ -638,22 +666,33 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
         const int T = (int)((G + 63) / 64);
         const unsigned rb = (unsigned)std::min<int64_t>((T + 3) / 4, 4096);
         const int long_bytes = long_seg ? (int)long_lds(&J, budget) : 0;
-        sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 0);
-        sat_setup_kernel<float><<<1, kPipedThreads, 0, st>>>(J);
+        if (lenq) {
+            sat_rebuild_kernel<float, LenQ><<<rb, 256, 0, st>>>(J, 0);
+            sat_setup_kernel<float, LenQ><<<1, kPipedThreads, 0, st>>>(J);
+        } else {
+            sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 0);
+            sat_setup_kernel<float><<<1, kPipedThreads, 0, st>>>(J);
+        }
         const int64_t n_seg = params->n_steps / params->resync_every + 1;
         const int sw = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         for (int64_t k = 0; k < n_seg; ++k) {
             if (piped_seg) {
                 PILA_TRY(launch1(tk ? ps->k_seg_tk : ps->k_seg, &J, waves * kWave, table_lds, st, &tm));
             } else if (long_seg) {
-                PILA_TRY(launch1(sat_long_segment_kernel<kLongE>, &J, params->m_cand * kWave, long_bytes,
-                                 st, &tm));
+                PILA_TRY(launch1(lenq ? sat_long_segment_kernel<kLongE, LenQ> : sat_long_segment_kernel<kLongE>,
+                                 &J, params->m_cand * kWave, long_bytes, st, &tm));
             } else {
                 PILA_TRY(tm.mark(st));
-                sat_simple_segment_kernel<<<1, sw * kWave, 0, st>>>(J);
+                if (lenq)
+                    sat_simple_segment_kernel<LenQ><<<1, sw * kWave, 0, st>>>(J);
+                else
+                    sat_simple_segment_kernel<float><<<1, sw * kWave, 0, st>>>(J);
                 PILA_TRY(tm.mark(st));
             }
-            sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 1);
+            if (lenq)
+                sat_rebuild_kernel<float, LenQ><<<rb, 256, 0, st>>>(J, 1);
+            else
+                sat_rebuild_kernel<float><<<rb, 256, 0, st>>>(J, 1);
             sat_resync_finish_kernel<<<1, 64, 0, st>>>(J);
         }
         sat_final_kernel<<<1, 1, 0, st>>>(J);
@@ -668,6 +707,8 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
         ChainKernel k;
         if (params->precision == PILA_F64)
             k = r_in_lds ? sat_long_kernel<double, true, kLongE> : sat_long_kernel<double, false, kLongE>;
+        else if (lenq)
+            k = r_in_lds ? sat_long_kernel<float, true, kLongE, LenQ> : sat_long_kernel<float, false, kLongE, LenQ>;
         else
             k = r_in_lds ? sat_long_kernel<float, true, kLongE> : sat_long_kernel<float, false, kLongE>;
         PILA_TRY(launch1(k, &J, params->m_cand * kWave, lds, st, &tm));
@@ -675,18 +716,19 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
         body = PILA_BODY_GENERAL | glob;
         waves = params->m_cand < kMaxWaves ? params->m_cand : kMaxWaves;
         const int lds = r_in_lds ? (int)(G * rs) : 0;
-        if (params->precision == PILA_F64) {
-            PILA_TRY(set_lds((const void*)sat_simple_kernel<double>, lds));
-            PILA_TRY(tm.mark(st));
-            sat_simple_kernel<double><<<1, waves * kWave, (size_t)lds, st>>>(J, lds);
-        } else {
-            PILA_TRY(set_lds((const void*)sat_simple_kernel<float>, lds));
-            PILA_TRY(tm.mark(st));
-            sat_simple_kernel<float><<<1, waves * kWave, (size_t)lds, st>>>(J, lds);
-        }
+        const void* k = params->precision == PILA_F64
+                            ? (lenq ? (const void*)sat_simple_kernel<double, LenQ>
+                                    : (const void*)sat_simple_kernel<double>)
+                            : (lenq ? (const void*)sat_simple_kernel<float, LenQ>
+                                    : (const void*)sat_simple_kernel<float>);
+        PILA_TRY(set_lds(k, lds));
+        PILA_TRY(tm.mark(st));
+        void* args[] = {&J, (void*)&lds};
+        PILA_HIP(hipLaunchKernel(k, dim3(1), dim3(waves * kWave), args, (size_t)lds, st));
         PILA_TRY(tm.mark(st));
     }
     PILA_HIP(hipGetLastError());
+    if (body_out) *body_out = body;
     if (h_stats) {
         PILA_HIP(hipMemcpyAsync(h_stats, J.stats, sizeof(sat_stats), hipMemcpyDeviceToHost, st));
         PILA_HIP(hipStreamSynchronize(st));
@@ -813,28 +855,48 @@ extern "C" int32_t sat_batch_workspace_size(int32_t n_jobs, const sat_job* jobs,
 }
 
 struct BatchGroup {
-    int kind;                       // PILA_BODY_PIPED, _LONG or _GENERAL
+    int kind;                       // PILA_BODY_PIPED, _LONG or _GENERAL (+256: FP64)
     const BatchShape* shape;        // the pipelined register shape (kind PIPED)
+    int waves;                      // wavefronts per chain
     std::vector<int> ids;           // its chains, longest first
     double longest = 0.0;           // estimated work of its longest chain
 };
 
-extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch,
-                                 void* d_ws, size_t ws_bytes, sat_stats* h_stats, void* stream)
+// What the host decides about a batch: chain descriptors, groups and their
+// order, the slot words to compute, and where each lives in the workspace.
+struct BatchPlan {
+    int32_t n_jobs = 0;
+    std::vector<ChainJob> host;
+    std::vector<BatchGroup> groups;
+    std::vector<int> order;
+    struct Tcol {
+        ChainJob J;
+        int64_t nnz;
+        int32_t* dst;
+    };
+    std::vector<Tcol> tcols;
+    ChainJob* d_jobs = nullptr;
+    int* d_ticket = nullptr;
+    int* d_order = nullptr;
+    int lds = 0, n_cu = 0, per_cu = 1;
+};
+
+static int32_t batch_plan(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch, void* d_ws,
+                          size_t ws_bytes, BatchPlan* bp)
 {
-    clear_error();
     size_t need = 0;
     PILA_TRY(sat_batch_workspace_size(n_jobs, jobs, &need));
     if (!d_ws || ws_bytes < need)
         return fail(PILA_ENOMEM, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
+    bp->n_jobs = n_jobs;
     if (n_jobs == 0) return PILA_OK;
-    hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)d_ws;
-    ChainJob* d_jobs = (ChainJob*)ws;
-    int* d_ticket = (int*)(ws + align256(sizeof(ChainJob) * (size_t)n_jobs));
-    int* d_order = d_ticket + kMaxGroups;
+    bp->d_jobs = (ChainJob*)ws;
+    bp->d_ticket = (int*)(ws + align256(sizeof(ChainJob) * (size_t)n_jobs));
+    bp->d_order = bp->d_ticket + kMaxGroups;
     char* cur = ws + align256(sizeof(ChainJob) * (size_t)n_jobs) + align256(sizeof(int) * (kMaxGroups + (size_t)n_jobs));
-    std::vector<ChainJob> host((size_t)n_jobs);
+    std::vector<ChainJob>& host = bp->host;
+    host.resize((size_t)n_jobs);
     for (int32_t j = 0; j < n_jobs; ++j) {
         const sat_job& jb = jobs[j];
         PILA_TRY(check_params(jb.geom, jb.csr, &jb.params));
@@ -842,14 +904,17 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         host[j] = make_job(jb.geom, jb.csr, jb.d_sino, &jb.params, jb.d_image, cur);
         cur += chain_bytes(jb.geom, &jb.params);
     }
-    int waves = 4, per_cu = 2, use_lds = 1;
+    int launch_waves = 4, per_cu = 2, use_lds = 1;
     if (launch) {
-        waves = launch->waves_per_chain;
+        launch_waves = launch->waves_per_chain;
         per_cu = launch->chains_per_cu;
         use_lds = launch->lds_residual;
     }
-    if (waves != 1 && waves != 2 && waves != 4 && waves != 8 && waves != 16)
-        return fail(PILA_EINVAL, "waves_per_chain must be 1, 2, 4, 8 or 16");
+    auto waves_ok = [](int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; };
+    if (!waves_ok(launch_waves)) return fail(PILA_EINVAL, "waves_per_chain must be 1, 2, 4, 8 or 16");
+    for (int32_t j = 0; j < n_jobs; ++j)
+        if (jobs[j].waves_per_chain != 0 && !waves_ok(jobs[j].waves_per_chain))
+            return fail(PILA_EINVAL, "job %d: waves_per_chain must be 0, 1, 2, 4, 8 or 16", j);
     if (per_cu < 1 || per_cu > 32) return fail(PILA_EINVAL, "chains_per_cu must be in 1..32");
     hipDeviceProp_t prop;
     PILA_TRY(device_props(&prop));
@@ -858,6 +923,9 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         const int per_wg = (int)(prop.sharedMemPerBlock / (size_t)per_cu) - (int)sizeof(ChainShared) - 512;
         lds = per_wg > 0 ? (per_wg & ~255) : 0;
     }
+    bp->lds = lds;
+    bp->n_cu = prop.multiProcessorCount;
+    bp->per_cu = per_cu;
     // estimated work of a chain: steps x estimates x mean row length
     auto work = [&](int j) {
         const double row = jobs[j].csr->n_support > 0
@@ -868,22 +936,23 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     // each chain's body: the pipelined body at the smallest register shape
     // that holds its rows (the fewest estimates per wavefront first), else
     // the long-row body, else the general body
-    std::vector<BatchGroup> groups;
-    auto group_of = [&](int kind, const BatchShape* shape) -> BatchGroup& {
+    std::vector<BatchGroup>& groups = bp->groups;
+    auto group_of = [&](int kind, const BatchShape* shape, int w) -> BatchGroup& {
         for (BatchGroup& g : groups)
-            if (g.kind == kind && g.shape == shape) return g;
-        groups.push_back(BatchGroup{kind, shape, {}, 0.0});
+            if (g.kind == kind && g.shape == shape && g.waves == w) return g;
+        groups.push_back(BatchGroup{kind, shape, w, {}, 0.0});
         return groups.back();
     };
     for (int32_t j = 0; j < n_jobs; ++j) {
         ChainJob& J = host[j];
+        const int waves = jobs[j].waves_per_chain ? jobs[j].waves_per_chain : launch_waves;
         const bool ahead = J.proposal == PILA_PROP_CLAMP;
         const bool fits = ahead && waves * kWave <= kPipedThreads;
         const BatchShape* bs = nullptr;
         if (fits && piped_allowed(jobs[j].geom, jobs[j].csr)) {
             for (int cpw : {1, 2, 4}) {
                 if (J.m_cand > waves * cpw) continue;
-                for (const BatchShape& sp : batch_shapes(J.precision))
+                for (const BatchShape& sp : batch_shapes(J.precision, J.lenq != 0))
                     if (sp.cpw == cpw && J.max_row <= (kWave / cpw) * sp.e) {
                         bs = &sp;
                         break;
@@ -895,13 +964,15 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         int kind = PILA_BODY_GENERAL;
         if (bs) {
             kind = PILA_BODY_PIPED;
-        } else if (fits && J.m_cand <= waves && long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params)) {
+        } else if (fits && J.m_cand <= waves && long_allowed(jobs[j].geom, jobs[j].csr, &jobs[j].params) &&
+                   !(J.lenq && J.precision == PILA_F64)) {
             long_lds(&J, lds);
             kind = PILA_BODY_LONG;
         } else {
             J.UL = 0;
         }
-        BatchGroup& g = group_of(kind | (J.precision == PILA_F64 ? 256 : 0), bs);
+        const int lq = kind != PILA_BODY_PIPED && J.lenq ? 512 : 0;  // (the piped shape says it)
+        BatchGroup& g = group_of(kind | (J.precision == PILA_F64 ? 256 : 0) | lq, bs, waves);
         g.ids.push_back(j);
         g.longest = std::max(g.longest, work(j));
     }
@@ -914,31 +985,38 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
     std::stable_sort(groups.begin(), groups.end(),
                      [](const BatchGroup& a, const BatchGroup& b) { return a.longest > b.longest; });
     // slot words of the pipelined chains' PILAs (the pipelined kernels read them)
-    {
-        const std::vector<const pila_csr*> tp = batch_tcol_pilas(n_jobs, jobs);
-        std::vector<int32_t*> where(tp.size(), nullptr);
-        for (const BatchGroup& g : groups) {
-            if (g.kind != PILA_BODY_PIPED) continue;  // FP32 pipelined groups only
-            for (int j : g.ids) {
-                size_t i = 0;
-                while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
-                if (i == tp.size()) return fail(PILA_EINVAL, "job %d: no slot-word room for its PILA", j);
-                if (!where[i]) {
-                    where[i] = (int32_t*)cur;
-                    cur += align256(sizeof(int32_t) * (size_t)tp[i]->nnz);
-                    PILA_TRY(launch_tcol(host[j], tp[i]->nnz, where[i], st));
-                }
-                host[j].tcol = where[i];
+    const std::vector<const pila_csr*> tp = batch_tcol_pilas(n_jobs, jobs);
+    std::vector<int32_t*> where(tp.size(), nullptr);
+    for (const BatchGroup& g : groups) {
+        if (g.kind != PILA_BODY_PIPED) continue;  // FP32 pipelined groups only
+        for (int j : g.ids) {
+            size_t i = 0;
+            while (i < tp.size() && tp[i]->col != jobs[j].csr->col) ++i;
+            if (i == tp.size()) return fail(PILA_EINVAL, "job %d: no slot-word room for its PILA", j);
+            if (!where[i]) {
+                where[i] = (int32_t*)cur;
+                cur += align256(sizeof(int32_t) * (size_t)tp[i]->nnz);
+                bp->tcols.push_back({host[j], tp[i]->nnz, where[i]});
             }
+            host[j].tcol = where[i];
         }
     }
-    std::vector<int> order;
-    for (const BatchGroup& g : groups) order.insert(order.end(), g.ids.begin(), g.ids.end());
-    PILA_HIP(hipMemcpyAsync(d_jobs, host.data(), sizeof(ChainJob) * host.size(), hipMemcpyHostToDevice, st));
-    PILA_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice, st));
-    zero_ints_kernel<<<1, 64, 0, st>>>(d_ticket, kMaxGroups);
+    for (const BatchGroup& g : groups) bp->order.insert(bp->order.end(), g.ids.begin(), g.ids.end());
+    return PILA_OK;
+}
+
+// The device work of a planned batch on stream st (descriptors and order
+// already in the workspace): ticket counters, slot words, then each group's
+// persistent kernel on its own stream forked from st and joined back into
+// it.  Capturable into a HIP graph (kernels and event dependencies only).
+// t_ev (nullable, 2 per group): events recorded around each group's kernel.
+static int32_t batch_enqueue(const BatchPlan& bp, hipStream_t st, hipEvent_t* t_ev)
+{
+    const std::vector<BatchGroup>& groups = bp.groups;
+    zero_ints_kernel<<<1, 64, 0, st>>>(bp.d_ticket, kMaxGroups);
     PILA_HIP(hipGetLastError());
-    // fork: every group after the first waits for the uploads on its own stream
+    for (const BatchPlan::Tcol& t : bp.tcols) PILA_TRY(launch_tcol(t.J, t.nnz, t.dst, st));
+    // fork: every group after the first waits for the work above on its own stream
     const int n_aux = (int)groups.size() - 1;
     hipStream_t aux[kMaxAux] = {};
     hipEvent_t fork = nullptr, join[kMaxAux] = {};
@@ -952,7 +1030,7 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
             for (int i = 0; i < n; ++i)
                 if (j[i]) (void)hipEventDestroy(j[i]);
         }
-    } cleanup{&fork, join, n_aux};
+    } cleanup{&fork, join, n_aux > 0 ? n_aux : 0};
     if (n_aux > 0) {
         PILA_TRY(aux_streams(n_aux, aux));
         PILA_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -962,6 +1040,68 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
             PILA_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
         }
     }
+    const ChainJob* jobs_arg = bp.d_jobs;
+    int lds_arg = bp.lds;
+    size_t first = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const BatchGroup& g = groups[gi];
+        hipStream_t gs = gi == 0 ? st : aux[gi - 1];
+        int n_arg = (int)g.ids.size();
+        const int* order_arg = bp.d_order + first;
+        int* ticket_arg = bp.d_ticket + gi;
+        first += g.ids.size();
+        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
+        const int grid = std::min(n_arg, bp.n_cu * bp.per_cu);
+        const int kind = g.kind & 255;
+        const bool f64 = (g.kind & 256) != 0;
+        const bool lq = (g.kind & 512) != 0;
+        const void* k = kind == PILA_BODY_PIPED ? (const void*)g.shape->k
+                        : kind == PILA_BODY_LONG
+                            ? (f64  ? (const void*)sat_batch_long_kernel<double, kLongE>
+                               : lq ? (const void*)sat_batch_long_kernel<float, kLongE, LenQ>
+                                    : (const void*)sat_batch_long_kernel<float, kLongE>)
+                        : f64 ? (lq ? (const void*)sat_batch_simple_kernel<double, LenQ>
+                                    : (const void*)sat_batch_simple_kernel<double>)
+                              : (lq ? (const void*)sat_batch_simple_kernel<float, LenQ>
+                                    : (const void*)sat_batch_simple_kernel<float>);
+        PILA_TRY(set_lds(k, bp.lds));
+        if (t_ev) PILA_HIP(hipEventRecord(t_ev[2 * gi], gs));
+        PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(g.waves * kWave), args, (size_t)bp.lds, gs));
+        if (t_ev) PILA_HIP(hipEventRecord(t_ev[2 * gi + 1], gs));
+        if (gi > 0) PILA_HIP(hipEventRecord(join[gi - 1], gs));
+    }
+    for (int i = 0; i < n_aux; ++i) PILA_HIP(hipStreamWaitEvent(st, join[i], 0));
+    PILA_HIP(hipGetLastError());
+    return PILA_OK;
+}
+
+// the body code of each chain of a planned batch (PILA_BODY_* | shape | width)
+static void batch_bodies(const BatchPlan& bp, std::vector<int32_t>* body)
+{
+    body->assign((size_t)bp.n_jobs, 0);
+    for (const BatchGroup& g : bp.groups)
+        for (int j : g.ids) {
+            const ChainJob& J = bp.host[j];
+            const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
+            const int kind = g.kind & 255;
+            const bool glob = kind != PILA_BODY_GENERAL || rb > bp.lds;
+            (*body)[j] = kind | (glob ? PILA_BODY_GLOBAL_R : 0) |
+                         (g.shape ? (g.shape->cpw << 8) | (g.shape->e << 16) : 0) | (g.waves << 24);
+        }
+}
+
+extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch,
+                                 void* d_ws, size_t ws_bytes, sat_stats* h_stats, void* stream)
+{
+    clear_error();
+    BatchPlan bp;
+    PILA_TRY(batch_plan(n_jobs, jobs, launch, d_ws, ws_bytes, &bp));
+    if (n_jobs == 0) return PILA_OK;
+    hipStream_t st = (hipStream_t)stream;
+    PILA_HIP(hipMemcpyAsync(bp.d_jobs, bp.host.data(), sizeof(ChainJob) * bp.host.size(), hipMemcpyHostToDevice,
+                            st));
+    PILA_HIP(hipMemcpyAsync(bp.d_order, bp.order.data(), sizeof(int) * bp.order.size(), hipMemcpyHostToDevice,
+                            st));
     // HIP events around each group's kernel on its stream, when asked for
     const bool timed = launch && launch->max_groups > 0 && launch->h_group_ms;
     hipEvent_t t_ev[2 * kMaxGroups] = {};
@@ -974,55 +1114,23 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
         }
     } t_cleanup{t_ev};
     if (timed)
-        for (size_t i = 0; i < 2 * groups.size(); ++i) PILA_HIP(hipEventCreate(&t_ev[i]));
-    const ChainJob* jobs_arg = d_jobs;
-    int lds_arg = lds;
-    size_t first = 0;
-    for (size_t gi = 0; gi < groups.size(); ++gi) {
-        const BatchGroup& g = groups[gi];
-        hipStream_t gs = gi == 0 ? st : aux[gi - 1];
-        int n_arg = (int)g.ids.size();
-        const int* order_arg = d_order + first;
-        int* ticket_arg = d_ticket + gi;
-        first += g.ids.size();
-        void* args[] = {&jobs_arg, &order_arg, &n_arg, &ticket_arg, &lds_arg};
-        const int grid = std::min(n_arg, prop.multiProcessorCount * per_cu);
-        const int kind = g.kind & 255;
-        const bool f64 = (g.kind & 256) != 0;
-        const void* k = kind == PILA_BODY_PIPED ? (const void*)g.shape->k
-                        : kind == PILA_BODY_LONG
-                            ? (f64 ? (const void*)sat_batch_long_kernel<double, kLongE>
-                                   : (const void*)sat_batch_long_kernel<float, kLongE>)
-                            : (const void*)sat_batch_simple_kernel;
-        PILA_TRY(set_lds(k, lds));
-        if (timed) PILA_HIP(hipEventRecord(t_ev[2 * gi], gs));
-        PILA_HIP(hipLaunchKernel(k, dim3(grid), dim3(waves * kWave), args, (size_t)lds, gs));
-        if (timed) PILA_HIP(hipEventRecord(t_ev[2 * gi + 1], gs));
-        if (gi > 0) PILA_HIP(hipEventRecord(join[gi - 1], gs));
-    }
-    for (int i = 0; i < n_aux; ++i) PILA_HIP(hipStreamWaitEvent(st, join[i], 0));
-    PILA_HIP(hipGetLastError());
+        for (size_t i = 0; i < 2 * bp.groups.size(); ++i) PILA_HIP(hipEventCreate(&t_ev[i]));
+    PILA_TRY(batch_enqueue(bp, st, timed ? t_ev : nullptr));
     if (h_stats) {
         for (int32_t j = 0; j < n_jobs; ++j)
-            PILA_HIP(hipMemcpyAsync(&h_stats[j], host[j].stats, sizeof(sat_stats), hipMemcpyDeviceToHost, st));
+            PILA_HIP(hipMemcpyAsync(&h_stats[j], bp.host[j].stats, sizeof(sat_stats), hipMemcpyDeviceToHost, st));
     }
     // the descriptor upload reads host memory owned by this call
     PILA_HIP(hipStreamSynchronize(st));
     if (h_stats) {
-        for (const BatchGroup& g : groups)
-            for (int j : g.ids) {
-                const ChainJob& J = host[j];
-                const int64_t rb = (int64_t)J.U * J.K * (J.precision == PILA_F32 ? 4 : 8);
-                const int kind = g.kind & 255;
-                const bool glob = kind != PILA_BODY_GENERAL || rb > lds;
-                h_stats[j].body = kind | (glob ? PILA_BODY_GLOBAL_R : 0) |
-                                  (g.shape ? (g.shape->cpw << 8) | (g.shape->e << 16) : 0);
-            }
+        std::vector<int32_t> body;
+        batch_bodies(bp, &body);
+        for (int32_t j = 0; j < n_jobs; ++j) h_stats[j].body = body[j];
     }
     if (launch && launch->max_groups > 0) {
         for (int i = 0; i < launch->max_groups; ++i) {
-            const bool have = i < (int)groups.size();
-            const BatchGroup* g = have ? &groups[i] : nullptr;
+            const bool have = i < (int)bp.groups.size();
+            const BatchGroup* g = have ? &bp.groups[i] : nullptr;
             if (launch->h_group_ms) {
                 float ms = 0.0f;
                 if (have && timed) PILA_HIP(hipEventElapsedTime(&ms, t_ev[2 * i], t_ev[2 * i + 1]));
@@ -1030,9 +1138,118 @@ extern "C" int32_t sat_run_batch(int32_t n_jobs, const sat_job* jobs, const sat_
             }
             if (launch->h_group_desc)
                 launch->h_group_desc[i] =
-                    have ? (g->kind & 255) | (g->shape ? (g->shape->cpw << 8) | (g->shape->e << 16) : 0) : 0;
+                    have ? (g->kind & 255) | (g->shape ? (g->shape->cpw << 8) | (g->shape->e << 16) : 0) |
+                               (g->waves << 24)
+                         : 0;
             if (launch->h_group_chains) launch->h_group_chains[i] = have ? (int)g->ids.size() : 0;
         }
     }
     return PILA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graphs: a chain's or a batch's launches captured once and replayed
+// ---------------------------------------------------------------------------
+struct sat_graph_s {
+    hipGraphExec_t exec = nullptr;
+    std::vector<sat_stats*> stats;  // where each chain's statistics land in the workspace
+    std::vector<int32_t> body;
+};
+
+// capture what enqueue() puts on a private stream into an instantiated graph
+template <typename F>
+static int32_t capture_graph(F enqueue, hipGraphExec_t* exec)
+{
+    hipStream_t cap = nullptr;
+    PILA_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{cap};
+    PILA_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    const int32_t rc = enqueue(cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (rc != PILA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+    const hipError_t ei = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate", __FILE__, __LINE__);
+    return PILA_OK;
+}
+
+extern "C" int32_t sat_graph_create(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
+                                    const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,
+                                    const sat_trace* trace, sat_graph** out)
+{
+    clear_error();
+    if (!out) return fail(PILA_EINVAL, "out is NULL");
+    *out = nullptr;
+    PILA_TRY(check_params(geom, csr, params));
+    auto g = std::make_unique<sat_graph_s>();
+    int body = 0;
+    PILA_TRY(capture_graph(
+        [&](hipStream_t cap) {
+            return sat_run_impl(geom, csr, d_sino, params, d_image, d_ws, ws_bytes, nullptr, trace, cap, false,
+                                &body);
+        },
+        &g->exec));
+    const ChainJob J = make_job(geom, csr, d_sino, params, d_image, (char*)d_ws);
+    g->stats.push_back(J.stats);
+    g->body.push_back(body);
+    *out = g.release();
+    return PILA_OK;
+}
+
+extern "C" int32_t sat_batch_graph_create(int32_t n_jobs, const sat_job* jobs, const sat_launch* launch,
+                                          void* d_ws, size_t ws_bytes, sat_graph** out)
+{
+    clear_error();
+    if (!out) return fail(PILA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_jobs < 1) return fail(PILA_EINVAL, "a batch graph needs at least one job");
+    BatchPlan bp;
+    PILA_TRY(batch_plan(n_jobs, jobs, launch, d_ws, ws_bytes, &bp));
+    // descriptors and order go to the workspace once, before the capture
+    PILA_HIP(hipMemcpy(bp.d_jobs, bp.host.data(), sizeof(ChainJob) * bp.host.size(), hipMemcpyHostToDevice));
+    PILA_HIP(hipMemcpy(bp.d_order, bp.order.data(), sizeof(int) * bp.order.size(), hipMemcpyHostToDevice));
+    auto g = std::make_unique<sat_graph_s>();
+    PILA_TRY(capture_graph([&](hipStream_t cap) { return batch_enqueue(bp, cap, nullptr); }, &g->exec));
+    for (const ChainJob& J : bp.host) g->stats.push_back(J.stats);
+    batch_bodies(bp, &g->body);
+    *out = g.release();
+    return PILA_OK;
+}
+
+extern "C" int32_t sat_graph_launch(sat_graph* g, void* stream)
+{
+    clear_error();
+    if (!g || !g->exec) return fail(PILA_EINVAL, "graph is NULL");
+    PILA_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return PILA_OK;
+}
+
+extern "C" int32_t sat_graph_stats(sat_graph* g, sat_stats* h_stats, void* stream)
+{
+    clear_error();
+    if (!g || !h_stats) return fail(PILA_EINVAL, "graph or stats is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t i = 0; i < g->stats.size(); ++i)
+        PILA_HIP(hipMemcpyAsync(&h_stats[i], g->stats[i], sizeof(sat_stats), hipMemcpyDeviceToHost, st));
+    PILA_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < g->stats.size(); ++i) h_stats[i].body = g->body[i];
+    return PILA_OK;
+}
+
+extern "C" int32_t sat_graph_destroy(sat_graph* g)
+{
+    clear_error();
+    if (!g) return PILA_OK;
+    hipError_t e = hipSuccess;
+    if (g->exec) e = hipGraphExecDestroy(g->exec);
+    delete g;
+    return e == hipSuccess ? PILA_OK : hip_fail(e, "hipGraphExecDestroy", __FILE__, __LINE__);
 }

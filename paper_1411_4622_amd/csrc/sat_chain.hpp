@@ -57,7 +57,8 @@ struct ChainJob {
     int32_t k_lo, Kc, UL, proposal;  // LDS part of the residual: angles u < UL, bins k_lo ..
                                      // k_lo+Kc-1; proposal: PILA_PROP_* (clamp or redraw)
     uint32_t kdiv_m, kdiv_s;     // g / K = (g * kdiv_m) >> kdiv_s for g < 2^24 (kdiv_s = 0: divide)
-    int32_t rkb, rpad;           // global residual layout: 8-bin blocks per angle group (rpos)
+    int32_t rkb, lenq;           // global residual layout: 8-bin blocks per angle group (rpos);
+                                 // lenq: lengths are one byte each (LenQ)
     int64_t n_steps, resync_every;
     uint64_t seed, chain_id;
     double T0, TN, tn_ratio, delta_max, f_min, f_max, ln09;
@@ -134,7 +135,7 @@ __device__ __forceinline__ ChainJob uniform_job(const ChainJob& d)
 #define PILA_F(f) J.f = lane0(d.f);
     PILA_F(N) PILA_F(U) PILA_F(K) PILA_F(P) PILA_F(precision) PILA_F(m_cand) PILA_F(n_stages)
     PILA_F(q_auto) PILA_F(max_row) PILA_F(schedule) PILA_F(k_lo) PILA_F(Kc) PILA_F(UL) PILA_F(proposal)
-    PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(rkb) PILA_F(rpad) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
+    PILA_F(kdiv_m) PILA_F(kdiv_s) PILA_F(rkb) PILA_F(lenq) PILA_F(n_steps) PILA_F(resync_every) PILA_F(seed) PILA_F(chain_id)
     PILA_F(T0) PILA_F(TN) PILA_F(tn_ratio) PILA_F(delta_max) PILA_F(f_min) PILA_F(f_max) PILA_F(ln09)
     PILA_F(row_ptr) PILA_F(col) PILA_F(len) PILA_F(t_row_ptr) PILA_F(t_col) PILA_F(t_len)
     PILA_F(support) PILA_F(sino) PILA_F(f) PILA_F(r) PILA_F(tsum) PILA_F(tdrift) PILA_F(carry)
@@ -356,7 +357,7 @@ struct Schedule {
 
 // Draw one estimate (Step 2, Eq. 3 with a clamp to [f_min, f_max]) and return
 // its row sum (whole wavefront, canonical order) in every lane.
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint64_t c0, uint64_t c1,
                              uint64_t c2, int lane, int32_t* p_out, double* fn_out, double* d_out)
 {
@@ -379,7 +380,7 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
         if (fn > J.f_max) fn = J.f_max;
     }
     const double d = fn - fo;
-    const Real* len = (const Real*)J.len;
+    const LenT* len = (const LenT*)J.len;
     const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
     const Real dr = (Real)d;
     Real acc = 0;
@@ -393,7 +394,7 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
         for (int c = 0; c < U; ++c) {
             const int64_t q = q0 + (int64_t)c * kWave < e ? q0 + (int64_t)c * kWave : b;
             cc[c] = J.col[q];
-            ll[c] = len[q];
+            ll[c] = (Real)len[q];
         }
         Real rr[U];
 #pragma unroll
@@ -421,12 +422,12 @@ __device__ Real estimate_sum(const ChainJob& J, const Real* __restrict__ r, uint
 // butterfly over the quarter adds the 16 partials.  Lane j then holds ray
 // t*64 + j.  In-group and grid-wide rebuilds both run this function, so they
 // give the same bits.
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int t, bool measure,
                              int lane)
 {
     constexpr int U4 = 4;  // entries per lane in flight
-    const Real* tl = (const Real*)J.t_len;
+    const LenT* tl = (const LenT*)J.t_len;
     const int quarter = lane >> 4, ql = lane & 15;
     double mine = 0.0;
     for (int i = 0; i < 16; ++i) {
@@ -441,7 +442,7 @@ __device__ void rebuild_tile(const ChainJob& J, Real* __restrict__ r, int G, int
                 for (int c = 0; c < U4; ++c) {
                     const int64_t q = q0 + 16 * c < e ? q0 + 16 * c : b;
                     pc[c] = J.t_col[q];
-                    lc[c] = tl[q];
+                    lc[c] = (Real)tl[q];
                 }
                 double fv[U4];
 #pragma unroll
@@ -491,14 +492,14 @@ __device__ inline void tile_totals(const ChainJob& J, int G, bool measure, int l
 }
 
 // in-workgroup rebuild of the whole residual; returns (sse, drift) to all
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ void rebuild_in_group(const ChainJob& J, Real* r, ChainShared& sh, bool measure, int lane,
                                  int wave, int NW, double* sse, double* drift)
 {
     const int G = J.U * J.K;
     const int T = (G + kWave - 1) / kWave;
     __syncthreads();
-    for (int t = wave; t < T; t += NW) rebuild_tile<Real, GLOB>(J, r, G, t, measure, lane);
+    for (int t = wave; t < T; t += NW) rebuild_tile<Real, GLOB, LenT>(J, r, G, t, measure, lane);
     __syncthreads();
     if (wave == 0) {
         double s, d;
@@ -522,7 +523,7 @@ struct ChainState {
 
 // Eq. 8: T0 from q_auto uphill single-pixel estimates of the starting image
 // (Philox counter (q, 0, 2, 0)), summed in q order.
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, ChainShared& sh, int lane,
                                  int wave, int NW, double* T0, double* TN, int32_t* status)
 {
@@ -535,7 +536,7 @@ __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, C
         if (q < limit) {
             int32_t p;
             double fn, d;
-            const double S = (double)estimate_sum<Real, GLOB>(J, r, (uint64_t)q, 0, 2, lane, &p, &fn, &d);
+            const double S = (double)estimate_sum<Real, GLOB, LenT>(J, r, (uint64_t)q, 0, 2, lane, &p, &fn, &d);
             const double cn = sqrt(fmax(sse + S, 0.0) / KU), co = sqrt(sse / KU);
             const double den = cn + co;
             if (lane == 0) sh.S[wave] = den == 0.0 ? 0.0 : (S / KU) / den;
@@ -568,16 +569,17 @@ __device__ void auto_temperature(const ChainJob& J, const Real* r, double sse, C
 }
 
 // Step 1 and Eq. 8 inside the workgroup.
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ ChainState chain_setup(const ChainJob& J, Real* r, ChainShared& sh, int lane, int wave, int NW)
 {
     ChainState cs;
     double drift;
-    rebuild_in_group<Real, GLOB>(J, r, sh, false, lane, wave, NW, &cs.sse, &drift);
+    rebuild_in_group<Real, GLOB, LenT>(J, r, sh, false, lane, wave, NW, &cs.sse, &drift);
     cs.T0 = J.T0;
     cs.TN = J.TN;
     cs.status = PILA_OK;
-    if (!(cs.T0 > 0.0)) auto_temperature<Real, GLOB>(J, r, cs.sse, sh, lane, wave, NW, &cs.T0, &cs.TN, &cs.status);
+    if (!(cs.T0 > 0.0))
+        auto_temperature<Real, GLOB, LenT>(J, r, cs.sse, sh, lane, wave, NW, &cs.T0, &cs.TN, &cs.status);
     cs.n_steps = cs.status == PILA_OK ? J.n_steps : 0;
     cs.accepts = cs.accepts_nz = cs.since = cs.s_begin = 0;
     cs.resyncs = 0;
@@ -709,12 +711,12 @@ __device__ __forceinline__ void count_decision(const ChainJob& J, ChainState& cs
     }
 }
 
-template <typename Real, bool GLOB>
+template <typename Real, bool GLOB, typename LenT = Real>
 __device__ __forceinline__ void resync_in_group(const ChainJob& J, ChainState& cs, Real* r, ChainShared& sh,
                                                 int lane, int wave, int NW)
 {
     double sse64, drift;
-    rebuild_in_group<Real, GLOB>(J, r, sh, true, lane, wave, NW, &sse64, &drift);
+    rebuild_in_group<Real, GLOB, LenT>(J, r, sh, true, lane, wave, NW, &sse64, &drift);
     cs.drift_r = fmax(cs.drift_r, drift);
     const double ds = sse64 > 0.0 ? fabs(cs.sse - sse64) / sse64 : fabs(cs.sse - sse64);
     cs.drift_sse = fmax(cs.drift_sse, ds);
@@ -726,7 +728,7 @@ __device__ __forceinline__ void resync_in_group(const ChainJob& J, ChainState& c
 // ---------------------------------------------------------------------------
 // any row length, any M
 // ---------------------------------------------------------------------------
-template <typename Real, bool LDS>
+template <typename Real, bool LDS, typename LenT = Real>
 __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, bool segmented = false)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
@@ -735,7 +737,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
     Real* r = LDS ? (Real*)lds : (Real*)J.r;
     // segmented (global residual only): the chain state comes from the carry
     // and the chain returns when a resync is due, which then runs grid-wide
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !LDS>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !LDS, LenT>(J, r, sh, lane, wave, NW);
     Schedule sched;
     sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
     const bool f32 = sizeof(Real) == 4;
@@ -745,7 +747,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
         for (int m = wave; m < M; m += NW) {
             int32_t p;
             double fn, d;
-            const Real S = estimate_sum<Real, !LDS>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
+            const Real S = estimate_sum<Real, !LDS, LenT>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
             if (lane == 0) {
                 sh.S[m] = (double)S;
                 sh.p[m] = p;
@@ -762,7 +764,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
         const double d_star = uniform_f64(sh.d[dn.ms]);
         if (dn.accept && wave == dn.ms % NW) {  // the owner of the winner applies Eq. 6
             const int32_t p = sh.p[dn.ms];
-            const Real* len = (const Real*)J.len;
+            const LenT* len = (const LenT*)J.len;
             const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
             const Real dr = (Real)d_star;
             // U entries per lane loaded before any is written (the row's rays
@@ -775,7 +777,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
                 for (int c = 0; c < U; ++c) {
                     const int64_t q = q0 + (int64_t)c * kWave < e ? q0 + (int64_t)c * kWave : b;
                     cc[c] = J.col[q];
-                    ll[c] = len[q];
+                    ll[c] = (Real)len[q];
                 }
                 uint32_t at[U];
 #pragma unroll
@@ -795,7 +797,7 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
                 save_carry(J, cs, s + 1, true);
                 return;
             }
-            resync_in_group<Real, !LDS>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !LDS, LenT>(J, cs, r, sh, lane, wave, NW);
         }
         __syncthreads();
         if (cancel_seen(J, sh, s)) {
@@ -888,7 +890,7 @@ __device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
 // TK: the rows' slot words come precomputed from J.tcol (loaded instead of
 // the ray indices, which are formed back from them where a global residual
 // value is read or written)
-template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false, bool TK = false>
+template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false, bool TK = false, typename LenT = Real>
 __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int LPC = kWave / CPW;  // lanes per estimate
@@ -909,9 +911,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     int64_t* pkey = (int64_t*)lds;
     Real* pval = (Real*)(lds + 16 * (size_t)J.U);
     Real* rl = (Real*)(lds + ((16 * (size_t)J.U + 2 * sizeof(Real) * (size_t)J.U + 15) & ~(size_t)15));
-    const Real* lenp = (const Real*)J.len;
+    const LenT* lenp = (const LenT*)J.len;
 
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS, LenT>(J, r, sh, lane, wave, NW);
     const int64_t n_steps = cs.n_steps;
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) {
@@ -994,7 +996,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 S.tk[e] = ld32(J.tcol, at);
             else
                 S.col[e] = ld32(J.col, at);
-            S.len[e] = ld32(lenp, at);
+            S.len[e] = (Real)ld32(lenp, at);
         }
     };
     // where each ray of a row lives: LDS index (flagged) or patch-table slot
@@ -1117,7 +1119,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 save_carry(J, cs, s + 1, true);
                 return true;
             }
-            resync_in_group<Real, !RLDS>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !RLDS, LenT>(J, cs, r, sh, lane, wave, NW);
             co = sqrt(cs.sse / KU);
             if (!RLDS) lds_residual_load<Real>(J, r, rl);
             // the next two sets are drawn again after the rebuild, so that no
@@ -1205,7 +1207,7 @@ struct LongRow {
     double delta, N1, lnN1;
 };
 
-template <typename Real, bool RLDS, int E, bool SERVED = false>
+template <typename Real, bool RLDS, int E, bool SERVED = false, typename LenT = Real>
 __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int BL = kWave;  // steps per block of draws: lane j <-> step base + j
@@ -1215,9 +1217,9 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
     const bool active = wave < M;
     Real* r = RLDS ? (Real*)lds : (Real*)J.r;
     Real* rl = (Real*)lds;
-    const Real* lenp = (const Real*)J.len;
+    const LenT* lenp = (const LenT*)J.len;
 
-    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS>(J, r, sh, lane, wave, NW);
+    ChainState cs = segmented ? load_carry(J) : chain_setup<Real, !RLDS, LenT>(J, r, sh, lane, wave, NW);
     const int64_t n_steps = cs.n_steps;
     const int64_t s_begin = cs.s_begin;
     if (!RLDS) lds_residual_load<Real>(J, r, rl);
@@ -1284,7 +1286,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
             const int q = lane + e * kWave;
             const uint32_t at = q < S.n ? b + (uint32_t)q : 0u;
             S.col[e] = ld32(J.col, at);
-            S.len[e] = ld32(lenp, at);
+            S.len[e] = (Real)ld32(lenp, at);
         }
     };
     // residual value of ray g: LDS part (angles u < UL: *lidx its index) or
@@ -1334,7 +1336,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
         // place, in the same per-lane order
         for (int q = kWave * E + lane; q < X.n; q += kWave) {
             int lo;
-            const Real t = dr * ld32(lenp, X.b + (uint32_t)q);
+            const Real t = dr * (Real)ld32(lenp, X.b + (uint32_t)q);
             part[0] = fma(t, (Real)2 * rget(ld32(J.col, X.b + (uint32_t)q), &lo) + t, part[0]);
         }
         const Real S = canon_sum<kWave>(part);
@@ -1366,7 +1368,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
             for (int q = kWave * E + lane; q < X.n; q += kWave) {
                 const int32_t g = ld32(J.col, X.b + (uint32_t)q);
                 int lo;
-                const Real rn = rget(g, &lo) + dr * ld32(lenp, X.b + (uint32_t)q);
+                const Real rn = rget(g, &lo) + dr * (Real)ld32(lenp, X.b + (uint32_t)q);
                 if (RLDS)
                     r[g] = rn;
                 else if (lo >= 0)
@@ -1386,7 +1388,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
                 save_carry(J, cs, s + 1, true);
                 return true;
             }
-            resync_in_group<Real, !RLDS>(J, cs, r, sh, lane, wave, NW);
+            resync_in_group<Real, !RLDS, LenT>(J, cs, r, sh, lane, wave, NW);
             if (!RLDS) lds_residual_load<Real>(J, r, rl);
         }
         __syncthreads();
@@ -1421,13 +1423,13 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
     write_stats(J, cs);
 }
 
-template <typename Real>
+template <typename Real, typename LenT = Real>
 __device__ void run_chain_simple_dispatch(const ChainJob& J, char* lds, int lds_bytes, ChainShared& sh)
 {
     if ((int64_t)J.U * J.K * (int64_t)sizeof(Real) <= lds_bytes)
-        run_chain_simple<Real, true>(J, lds, sh);
+        run_chain_simple<Real, true, LenT>(J, lds, sh);
     else
-        run_chain_simple<Real, false>(J, lds, sh);
+        run_chain_simple<Real, false, LenT>(J, lds, sh);
 }
 
 }  // namespace pila

@@ -654,6 +654,7 @@ extern "C" int32_t srv_prepare(srv_t* s, const pila_geom* geom)
     clear_error();
     if (!s) return fail(PILA_EINVAL, "server is NULL");
     PILA_TRY(check_geom(geom));
+    if (geom->len_dtype == PILA_U8) return fail(PILA_EINVAL, "the server keeps FP32 or FP64 lengths");
     std::lock_guard<std::mutex> lk(s->mu);
     PilaEntry* e = nullptr;
     return cache_get(s, geom, &e);
@@ -665,6 +666,7 @@ extern "C" int32_t srv_submit(srv_t* s, const srv_request* req, uint64_t* ticket
     if (!s || !req || !ticket) return fail(PILA_EINVAL, "server, request or ticket is NULL");
     if (!req->d_sino || !req->d_image) return fail(PILA_EINVAL, "sinogram or image is NULL");
     PILA_TRY(check_geom(req->geom));
+    if (req->geom->len_dtype == PILA_U8) return fail(PILA_EINVAL, "the server keeps FP32 or FP64 lengths");
     std::lock_guard<std::mutex> lk(s->mu);
     PILA_TRY(progress(s));
     PilaEntry* e = nullptr;

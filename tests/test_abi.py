@@ -130,6 +130,16 @@ def test_static_entry_refuses_oversized_chain(P):
     assert "static scratch" in P.last_error()
 
 
+def test_graph_argument_errors(P):
+    lib = P.load()
+    h = C.c_void_p()
+    assert lib.sat_graph_launch(None, None) == P._binding.PILA_EINVAL
+    assert lib.sat_graph_stats(None, None, None) == P._binding.PILA_EINVAL
+    assert lib.sat_graph_destroy(None) == 0
+    assert lib.sat_graph_create(None, None, None, None, None, None, 0, None, None) == P._binding.PILA_EINVAL
+    assert lib.sat_batch_graph_create(0, None, None, None, 0, C.byref(h)) == P._binding.PILA_EINVAL
+
+
 def test_workspace_sizes(P):
     lib = P.load()
     from paper_1411_4622_amd._binding import CSirtParams
