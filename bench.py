@@ -68,7 +68,12 @@ def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
 # kernel sources they were taken with (hash over the files below)
 TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
                    "paper_1411_4622_amd/csrc/common.hpp")
-TRAFFIC = {}
+TRAFFIC = {"kernel": "sat_batch_kernel<float,1,8>",
+           "sources_sha256": "4daee48ff54346cc0600872a2cef17e0edfc7f0a853caa4bf7803e1833b71801",
+           "fetch_kib": 13207995017.1875, "fetch_factor": 2.0,
+           "write_kib": 1151753098.90625, "write_factor": 1.0,
+           "bytes_per_dispatch": 13207995017.1875 * 1024 * 2.0 + 1151753098.90625 * 1024 * 1.0,
+           "profile": "profiles/sat_batch_kernel_c3_512slices.md"}
 
 
 def sources_hash() -> str:
