@@ -478,11 +478,18 @@ typedef struct srv_status {
 /*
  * srv_create - allocate the server on the current device: mem_budget bytes
  * of device memory, a ring of ring_size request descriptors in pinned host
- * memory, and non-blocking streams for the resident kernels.  No device
- * memory is allocated after this call (PILA builds use the budget too).
- * The resident kernels run while requests are in flight and for idle_us
- * after: a device-wide synchronisation (hipDeviceSynchronize) waits for
- * them, so callers synchronise their own streams instead.
+ * memory, and three non-blocking streams, one per resident kernel (PILA
+ * builds run on the null stream).  No device memory is allocated after this
+ * call (PILA builds use the budget too).  The resident kernels run while
+ * requests are in flight and for idle_us after: a device-wide
+ * synchronisation (hipDeviceSynchronize) waits for them, so callers
+ * synchronise their own streams instead.  HIP maps streams onto a few
+ * hardware queues (GPU_MAX_HW_QUEUES, 4 by default), each run in order: work
+ * on any stream that shares a hardware queue with a resident kernel waits
+ * until that kernel ends.  The three streams have hardware queues of their
+ * own when the process holds no more streams than hardware queues, counting
+ * the null stream: e.g. a caller that works on the null stream and creates
+ * the server before other streams; otherwise raise GPU_MAX_HW_QUEUES.
  * Errors: EINVAL (NULL arguments, bad sizes), ENOMEM (budget too small for
  * the server's own bookkeeping), EHIP.
  */

@@ -62,6 +62,13 @@ static_assert(sizeof(sat_stats) % 8 == 0, "stats are copied in 64-bit words");
 // general body (any row length, M, precision).
 enum { kPiped = 0, kGeneral = 1, kLong = 2 };
 
+// PILA builds and the claim counters' clears run on the null stream, so the
+// server adds only its three queue streams to the process.  HIP gives each
+// stream one of a few hardware queues (GPU_MAX_HW_QUEUES, 4 by default) and
+// a queue runs its work in order: anything behind a resident kernel on the
+// same hardware queue waits until that kernel ends.
+const hipStream_t kBuildStream = nullptr;
+
 // top bit of a queue's claim counter: the queue's kernel is ending
 constexpr unsigned long long kClosed = 1ull << 63;
 
@@ -331,7 +338,6 @@ struct srv_s {
     std::mutex mu;
     srv_config cfg{};
     int device = 0;
-    hipStream_t build_stream = nullptr;
     char* arena_base = nullptr;
     Arena arena;
     Block head_blk, scratch_blk;
@@ -442,14 +448,14 @@ int32_t cache_get(srv_t* s, const pila_geom* g, PilaEntry** out)
     };
     PILA_TRY(take(sizes1, dst1, 3));
     void* scratch = s->arena.at(s->scratch_blk.off);
-    PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, s->build_stream));
+    PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, kBuildStream));
     const size_t nnz = (size_t)std::max<int64_t>(e->csr.nnz, 1);
     const size_t sizes2[5] = {4 * nnz, ls * nnz, 4 * nnz, ls * nnz,
                               4 * (size_t)std::max(e->csr.n_support, 1)};
     void** dst2[5] = {(void**)&e->csr.col, &e->csr.len, (void**)&e->csr.t_col, &e->csr.t_len,
                       (void**)&e->csr.support};
     PILA_TRY(take(sizes2, dst2, 5));
-    PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, s->build_stream));
+    PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, kBuildStream));
     // FP32 rows the pipelined body can hold: the slot words of the entries
     // for the server's LDS layout (the same for every chain on this PILA)
     if (g->len_dtype == PILA_F32 && e->csr.max_row <= 512 && piped_allowed(&e->geom, &e->csr)) {
@@ -462,7 +468,9 @@ int32_t cache_get(srv_t* s, const pila_geom* g, PilaEntry** out)
         prm.n_stages = 1;
         ChainJob J = make_job(&e->geom, &e->csr, nullptr, &prm, nullptr, nullptr);
         hybrid_lds(&J, s->lds_bytes);
-        PILA_TRY(launch_tcol(J, e->csr.nnz, e->tcol, s->build_stream));
+        PILA_TRY(launch_tcol(J, e->csr.nnz, e->tcol, kBuildStream));
+        // the slot words are read by the queue's kernel on another stream
+        PILA_HIP(hipStreamSynchronize(kBuildStream));
     }
     e->last_use = ++s->use_clock;
     *out = e.get();
@@ -549,8 +557,6 @@ int32_t destroy_impl(srv_t* s)
         if (q.ctl) (void)hipHostFree(q.ctl);
         if (q.slots) (void)hipHostFree(q.slots);
     }
-    if (s->build_stream && hipStreamSynchronize(s->build_stream) != hipSuccess) rc = PILA_EHIP;
-    if (s->build_stream) (void)hipStreamDestroy(s->build_stream);
     if (s->arena_base) (void)hipFree(s->arena_base);
     delete s;
     return rc;
@@ -573,7 +579,7 @@ int32_t init_queue(srv_t* s, Queue& q, const RingShape* shape, int groups)
     PILA_HIP(hipHostGetDevicePointer((void**)&q.d_slots, q.slots, 0));
     PILA_HIP(hipStreamCreateWithFlags(&q.stream, hipStreamNonBlocking));
     PILA_HIP(hipEventCreateWithFlags(&q.done_ev, hipEventDisableTiming));
-    PILA_HIP(hipMemsetAsync(q.d_head, 0, 256, s->build_stream));
+    PILA_HIP(hipMemsetAsync(q.d_head, 0, 256, kBuildStream));
     return PILA_OK;
 }
 
@@ -630,8 +636,6 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     s->scratch_blk.len = align256(std::min<size_t>(256 + (size_t)2048 * 2048, cfg.mem_budget / 8));
     s->scratch_blk.off = s->arena.alloc(s->scratch_blk.len);
     if (s->scratch_blk.off == SIZE_MAX) return bail(fail(PILA_ENOMEM, "budget too small"));
-    if (hipStreamCreateWithFlags(&s->build_stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(PILA_EHIP, "cannot create the build stream"));
     // general_slots (default a sixteenth) and long_slots (default a quarter)
     // for those bodies, the pipelined body the rest
     const int gen = cfg.general_slots > 0 ? cfg.general_slots : std::max(1, cfg.max_slots / 16);
@@ -642,7 +646,7 @@ extern "C" int32_t srv_create(const srv_config* cfg_in, srv_t** out)
     if (rc == PILA_OK) rc = init_queue(s, s->q[kGeneral], general_shape(), gen);
     if (rc == PILA_OK) rc = init_queue(s, s->q[kLong], long_shape(), lng);
     if (rc != PILA_OK) return bail(rc);
-    if (hipStreamSynchronize(s->build_stream) != hipSuccess)
+    if (hipStreamSynchronize(kBuildStream) != hipSuccess)
         return bail(fail(PILA_EHIP, "cannot clear the claim counters"));
     s->fixed_bytes = s->arena.used();
     *out = s;
