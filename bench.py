@@ -49,16 +49,17 @@ def log(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int) -> float:
+def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int, len_bytes: int = 4) -> float:
     """Algorithmic bytes of one FP32 chain in a batch.
 
     per estimate: support index 4, image value 8, row offsets 16, and per row
-    entry slot word 4 + length 4 + residual 4; per accepted estimate: per row
-    entry slot word 4 + length 4 + residual read 4 + write 4, image write 8.
-    In-group FP64 resyncs (per PILA entry pixel 4 + length 4 + image 8) are
-    not counted.
+    entry slot word 4 + length (4, or 1 for one-byte lengths) + residual 4;
+    per accepted estimate: per row entry slot word 4 + length + residual read
+    4 + write 4, image write 8.  In-group FP64 resyncs (per PILA entry pixel
+    4 + length + image 8) are not counted.
     """
-    return n_steps * M * (28.0 + 12.0 * f_mean) + accepts * (8.0 + 16.0 * f_mean)
+    return (n_steps * M * (28.0 + (8.0 + len_bytes) * f_mean)
+            + accepts * (8.0 + (12.0 + len_bytes) * f_mean))
 
 
 # HBM bytes per dispatch of the kernel the roofline reports, from two
@@ -229,7 +230,7 @@ def run_c3(args) -> int:
     geoms = {}
     for sl in slices:
         if (sl.N, sl.U) not in geoms:
-            geoms[(sl.N, sl.U)] = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
+            geoms[(sl.N, sl.U)] = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, args.lengths)
     sinos = [torch.from_numpy(sl.sino).to(dev) for sl in slices]
     f0s = [torch.from_numpy(sl.f0).to(dev) for sl in slices]
     imgs = [torch.empty_like(f) for f in f0s]
@@ -390,7 +391,8 @@ def run_c3(args) -> int:
     # the timed steps); the whole batch beside it
     body_of = [s["body"] for s in st]
     acc = [s["accepts"] for s in st]
-    b_chain = [chain_bytes(params[c].n_steps, M, fmean[key_of[c]], acc[c]) for c in range(n)]
+    lb = 1 if args.lengths == "u8" else 4
+    b_chain = [chain_bytes(params[c].n_steps, M, fmean[key_of[c]], acc[c], lb) for c in range(n)]
     gdesc = [(g["kind"], g["cpw"], g["e"], g["waves"]) for g in group_runs[-1]]
     g_ms = {d: statistics.mean(next(g["ms"] for g in run if (g["kind"], g["cpw"], g["e"], g["waves"]) == d)
                                 for run in group_runs) for d in gdesc}
@@ -403,8 +405,10 @@ def run_c3(args) -> int:
     dom_chains = [c for c in range(n) if in_group(body_of[c], dom)]
     dom_bytes = sum(b_chain[c] for c in dom_chains)
     achieved = dom_bytes / (g_ms[dom] / 1e3) / 1e9
-    kname = {1: "sat_batch_kernel<float,%d,%d>" % (dom[1], dom[2]), 2: "sat_batch_long_kernel<float,16>",
-             3: "sat_batch_simple_kernel"}[dom[0]]
+    lt = ",LenQ" if args.lengths == "u8" else ""
+    kname = {1: "sat_batch_kernel<float,%d,%d%s>" % (dom[1], dom[2], lt),
+             2: "sat_batch_long_kernel<float,16%s>" % lt,
+             3: "sat_batch_simple_kernel<float%s>" % lt}[dom[0]]
     traffic = None
     if TRAFFIC and TRAFFIC.get("sources_sha256") == sources_hash() and TRAFFIC.get("kernel") == kname \
             and args.slices == 512 and args.sweeps is None:
@@ -431,6 +435,7 @@ def run_c3(args) -> int:
                                "(steps = sweeps x support), FP32 residual with FP64 resync, Eq. 8 T0, "
                                "tuned launch shape" % (n, sweeps),
                    "n_slices": n, "sweeps": sweeps, "M": M, "steps_total": steps_total,
+                   "lengths": {"f32": "FP32", "u8": "one byte, round(180 l)"}[args.lengths],
                    "geometries": {"%dx%d" % k: key_of.count(k) for k in keys}},
         "steps_per_s": args.steps * steps_total / wall,
         "slices_per_s": args.steps * n / wall,
@@ -470,10 +475,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=("c2", "c3", "c3r", "c4", "c5"),
+    ap.add_argument("--workload", default="c3", choices=("c2", "c3", "c3r", "c4", "c5", "bome", "drt"),
                     help="c3 (default): the batch line; c2: one chain; c3r: batch with repeated "
-                         "phantoms; c4: 1024^2 slice, SAT M=32 and SIRT; c5: serving stream")
+                         "phantoms; c4: 1024^2 slice, SAT M=32 and SIRT; c5: serving stream; bome: "
+                         "N_e and cooling-schedule sweeps; drt: PILA against the bilinear DRT")
     ap.add_argument("--slices", type=int, default=512, help="c3: slices in the batch")
+    ap.add_argument("--lengths", default="f32", choices=("f32", "u8"),
+                    help="c3: PILA lengths as FP32 or as one byte each (section II-B)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-sanity", action="store_true")

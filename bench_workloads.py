@@ -623,11 +623,171 @@ def run_c5(args, P, torch, datagen):
     return 0
 
 
+# ---------------------------------------------------------------------------
+# BoME and cooling schedules (sections III-B, III-C)
+# ---------------------------------------------------------------------------
+
+def _consistent_slice(P, torch, datagen, N, U, seed, n_ell=10):
+    """A phantom's pixel image and its Eq. 1 projections (noise-free data the
+    pixel model can fit), FP64 PILA, uniform start."""
+    K = datagen.n_bins_for(N)
+    ell = datagen.random_ellipses(seed, N, n_ell)
+    sl = datagen.make_slice(N, U, K, ell, masked=True, I0=None)
+    pl = P.pila_build(P.Geometry(N, sl.angles, K, sl.mask, "f64"))
+    truth = torch.from_numpy(sl.truth * sl.mask).cuda()
+    sino = P.pila_forward(pl, truth)
+    f0 = torch.from_numpy(datagen.uniform_start(sino.cpu().numpy(), sl.mask, N)).cuda()
+    return sl, pl, truth.cpu().numpy(), sino, f0
+
+
+def run_bome(args, P, torch, datagen):
+    """N_e and cooling-schedule sweeps on noise-free 64 x 64 data (U = 60):
+    1000 stages of 2000 steps, Eq. 8 T0, FP64; cost C (Eq. 4) at stages
+    100, 200, 500 and 1000 from the chain's trace and the final NRMSE; the
+    N_e = 1 chain with four times the steps of N_e = 4 (same evaluations);
+    and the final cost after 200 stages of one sweep each (steps = 200 x
+    support) for N = 32, 64, 128 with U = N."""
+    t_all = time.perf_counter()
+    sl, pl, truth, sino, f0 = _consistent_slice(P, torch, datagen, 64, 60, 106)
+    stages = 1000
+
+    def chain(Ne, schedule, steps, seed=1006):
+        im = f0.clone()
+        prm = P.SatParams(n_steps=steps, seed=seed, chain_id=Ne, n_stages=stages, m_cand=Ne, T0=None,
+                          q_auto=200, delta_max=0.05, schedule=schedule)
+        ts = time.perf_counter()
+        st, tr = P.sat_run(pl, sino, prm, im, trace=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ts
+        acc = tr["accept"].cpu().numpy().astype(bool)
+        dc = tr["dC"].cpu().numpy()
+        # C after each step: the start cost plus the accepted changes
+        c_start = st["cost_final"] - float(np.sum(dc[acc]))
+        c_path = c_start + np.cumsum(np.where(acc, dc, 0.0))
+        at = {str(k): float(c_path[k * steps // stages - 1]) for k in (100, 200, 500, 1000)}
+        f = im.cpu().numpy()
+        return {"N_e": Ne, "schedule": schedule, "steps": steps, "cost_at_stage": at,
+                "cost_final": st["cost_final"], "nrmse": datagen.nrmse(f, truth), "accepts": st["accepts"],
+                "T0": st["T0_used"], "seconds": dt}
+
+    sweep = []
+    for schedule in ("linear", "exp", "cubic"):
+        for Ne in (1, 2, 4, 8, 16, 32):
+            r = chain(Ne, schedule, 2_000_000)
+            sweep.append(r)
+            log("bome: %s N_e=%d NRMSE %.4f C %.3g (stage 200: %.3g) %.1f s" % (
+                schedule, Ne, r["nrmse"], r["cost_final"], r["cost_at_stage"]["200"], r["seconds"]))
+    same_evals = chain(1, "linear", 8_000_000)
+    log("bome: N_e=1 with 8e6 steps: NRMSE %.4f" % same_evals["nrmse"])
+
+    # final cost against N_e for three sizes, all chains in one batch
+    sizes = []
+    jobs, meta = [], []
+    for N in (32, 64, 128):
+        sl2, pl2, truth2, sino2, f02 = _consistent_slice(P, torch, datagen, N, N, 200 + N)
+        sup = int(sl2.mask.sum())
+        for Ne in (1, 2, 4, 8, 16, 32):
+            im = f02.clone()
+            prm = P.SatParams(n_steps=200 * sup, seed=77, chain_id=Ne, n_stages=200, m_cand=Ne, T0=None,
+                              q_auto=200, delta_max=0.05)
+            jobs.append(P.Job(pl2, sino2, im, prm))
+            meta.append((N, Ne, truth2))
+    ts = time.perf_counter()
+    st = P.sat_run_batch(jobs, waves_per_chain=8, chains_per_cu=1)
+    torch.cuda.synchronize()
+    for (N, Ne, truth2), j, s_ in zip(meta, jobs, st):
+        sizes.append({"N": N, "U": N, "N_e": Ne, "steps": j.params.n_steps, "cost_final": s_["cost_final"],
+                      "nrmse": datagen.nrmse(j.image.cpu().numpy(), truth2)})
+    log("bome: size sweep (18 chains, one batch) in %.1f s" % (time.perf_counter() - ts))
+    out = {"metric": "final NRMSE and cost C (Eq. 4) against N_e and cooling schedule",
+           "workload": "noise-free 64x64 (10 ellipses, its pixel image projected by Eq. 1), U=60, K=91, "
+                       "1000 stages x 2000 steps, change in [-0.05, 0.05) clamped to [0, 1], Eq. 8 T0, FP64",
+           "sweep": sweep, "N_e1_same_evaluations_as_N_e4": same_evals,
+           "size_sweep": {"setting": "200 stages of one sweep each (steps = 200 x support), U = N, Eq. 8 T0",
+                          "results": sizes},
+           "seconds": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# ---------------------------------------------------------------------------
+# the PILA against the bilinear DRT (section III-A, Fig. 3)
+# ---------------------------------------------------------------------------
+
+def run_drt(args, P, torch, datagen):
+    """Time per SA step with the PILA (sat_run, N_e = 1; FP64, and FP32 with
+    FP64 resyncs) and with the bilinear discrete Radon transform of the
+    whole image per estimate (sat_drt_run, FP64), for N = 64 .. 512 and U =
+    90, 180, 360: 200 steps as in the paper (N = 1, M = 200) for the DRT
+    chain, the PILA chains timed on 20000 steps for a stable rate; the gain
+    is the ratio of the per-step times, and also of the 200-step totals with
+    the FP64 PILA build included."""
+    res = []
+    for N in (64, 128, 256, 512):
+        for U in (90, 180, 360):
+            K = datagen.n_bins_for(N)
+            ell = datagen.random_ellipses(300 + N, N, 8)
+            sl = datagen.make_slice(N, U, K, ell, masked=True, I0=1e4, noise_seed=N + U)
+            sino = torch.from_numpy(sl.sino).cuda()
+            f0 = torch.from_numpy(sl.f0).cuda()
+            geom = P.Geometry(N, sl.angles, K, sl.mask, "f64")
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            pl = P.pila_build(geom)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - ts
+
+            pl32 = P.pila_build(P.Geometry(N, sl.angles, K, sl.mask, "f32"))
+
+            def pila_time(steps, prec="f64"):
+                im = f0.clone()
+                prm = P.SatParams(n_steps=steps, seed=5, m_cand=1, T0=1e-2, TN=1e-6, n_stages=100,
+                                  precision=prec, resync_every=4096 if prec == "f32" else 0)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                P.sat_run(pl if prec == "f64" else pl32, sino, prm, im, stats=False)
+                e1.record()
+                e1.synchronize()
+                return e0.elapsed_time(e1) / 1e3
+
+            pila_time(2000)
+            pila_time(2000, "f32")
+            t_pila_200 = pila_time(200)
+            t_pila = pila_time(20000) / 20000
+            t_pila32 = pila_time(20000, "f32") / 20000
+            im = f0.clone()
+            prm = P.SatParams(n_steps=200, seed=5, m_cand=1, T0=1e-2, TN=1e-6, n_stages=100)
+            P.sat_drt_run(geom, sino, prm, im)  # warm-up
+            im = f0.clone()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            P.sat_drt_run(geom, sino, prm, im)
+            torch.cuda.synchronize()
+            t_drt = (time.perf_counter() - ts) / 200
+            r = {"N": N, "U": U, "K": K, "pila_nnz": pl.nnz, "pila_build_s": t_build,
+                 "pila_us_per_step": 1e6 * t_pila, "pila_f32_us_per_step": 1e6 * t_pila32,
+                 "drt_us_per_step": 1e6 * t_drt,
+                 "gain_per_step": t_drt / t_pila, "gain_per_step_f32": t_drt / t_pila32,
+                 "gain_200_steps_with_build": 200 * t_drt / (t_pila_200 + t_build)}
+            res.append(r)
+            log("drt: N=%d U=%d: PILA %.2f us/step (FP32 %.2f), DRT %.1f us/step, gain %.0fx (FP32 %.0fx; "
+                "%.0fx with the build)" % (N, U, r["pila_us_per_step"], r["pila_f32_us_per_step"],
+                                           r["drt_us_per_step"], r["gain_per_step"], r["gain_per_step_f32"],
+                                           r["gain_200_steps_with_build"]))
+            del pl, pl32
+    out = {"metric": "SA step time: PILA against the bilinear DRT (section III-A)",
+           "setting": "one chain, N_e=1, given T0/TN, Poisson I0=1e4 data; DRT chain (FP64) 200 steps "
+                      "(N=1, M=200), PILA chains (FP64; FP32 with FP64 resync) timed on 20000 steps",
+           "paper": "gain over 300x for the largest sizes on its CPU (Fig. 3)", "results": res}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def run(args) -> int:
     import torch
     import datagen
     import paper_1411_4622_amd as P
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
-    return {"c2": run_c2, "c3r": run_c3_repeat, "c4": run_c4,
-            "c5": run_c5}[args.workload](args, P, torch, datagen)
+    return {"c2": run_c2, "c3r": run_c3_repeat, "c4": run_c4, "c5": run_c5, "bome": run_bome,
+            "drt": run_drt}[args.workload](args, P, torch, datagen)

@@ -370,7 +370,9 @@ __global__ __launch_bounds__(kPipedThreads) void sat_batch_kernel(
         __syncthreads();
         if (j >= n_jobs) break;
         const int64_t t0 = (int64_t)wall_clock64();
-        const ChainJob J = uniform_job(jobs[order[j]]);  // fields in scalar registers
+        // the descriptor stays in memory, read by scalar loads where a field
+        // is used (a copy in registers holds every field live: spills)
+        const ChainJob& J = jobs[__builtin_amdgcn_readfirstlane(order[j])];
         run_chain_piped<Real, false, CPW, E, false, sizeof(Real) == 4, LenT>(J, lds, sh, false);
         stamp_chain(J, t0);
     }
