@@ -70,10 +70,10 @@ def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int, len_bytes: in
 TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
                    "paper_1411_4622_amd/csrc/common.hpp")
 TRAFFIC = {"kernel": "sat_batch_kernel<float,1,8>",
-           "sources_sha256": "4daee48ff54346cc0600872a2cef17e0edfc7f0a853caa4bf7803e1833b71801",
-           "fetch_kib": 13207995017.1875, "fetch_factor": 2.0,
-           "write_kib": 1151753098.90625, "write_factor": 1.0,
-           "bytes_per_dispatch": 13207995017.1875 * 1024 * 2.0 + 1151753098.90625 * 1024 * 1.0,
+           "sources_sha256": "fc6e7be2fe2b7c66aa881dfda92b9e1dd9e11223667b73c46750c777ef4c08cb",
+           "fetch_kib": 13073290924.0625, "fetch_factor": 524288.0 / 262155.5,
+           "write_kib": 1118302744.6875, "write_factor": 1.0,
+           "bytes_per_dispatch": 13073290924.0625 * 1024 * (524288.0 / 262155.5) + 1118302744.6875 * 1024 * 1.0,
            "profile": "profiles/sat_batch_kernel_c3_512slices.md"}
 
 
