@@ -7,7 +7,7 @@ Workload (default): a batch of 512 independent slices cut from one seeded
 ceil(sqrt(2) N) unit bins, photon noise at I0 = 1e4 per ray, circular
 support; one annealing chain per slice: best of M = 8 estimates per step,
 16 sweeps of the support (steps = 16 x support pixels), FP32 residual
-rebuilt in FP64 every max(4096, nnz / 1024) accepted nonzero changes, T0
+rebuilt in FP64 every max(4096, nnz / 128) accepted nonzero changes, T0
 from Eq. 8 (Q = 200), T_N = T0 / 1e3, linear cooling over 1000 stages.
 
 One benchmark step is one pass of the whole path over that batch: the nine
@@ -68,7 +68,7 @@ def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int, len_bytes: in
 # known size of a plain device copy in the same run; valid only for the
 # kernel sources they were taken with (hash over the files below)
 TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
-                   "paper_1411_4622_amd/csrc/common.hpp")
+                   "paper_1411_4622_amd/csrc/common.hpp", "bench_workloads.py")
 TRAFFIC = {"kernel": "sat_batch_kernel<float,1,8>",
            "sources_sha256": "fc6e7be2fe2b7c66aa881dfda92b9e1dd9e11223667b73c46750c777ef4c08cb",
            "fetch_kib": 13073290924.0625, "fetch_factor": 524288.0 / 262155.5,

@@ -51,10 +51,11 @@ def _pool_map(fn, items, procs=16):
 def resync_interval(cfg, nnz):
     """Accepted nonzero changes between FP64 resyncs for the batch and serving
     workloads, which do not fix it: at least the configured 4096, and at
-    least nnz / 1024.  Their resyncs run inside the chain's workgroup, where
-    a full-PILA rebuild reads about 17 GB/s (one CU, bound by its gathers);
-    nnz / 1024 keeps it near a tenth of the chain's time."""
-    return max(int(cfg["resync_every"]), int(nnz) // 1024)
+    least nnz / 128.  Their resyncs run inside the chain's workgroup, where a
+    full-PILA rebuild takes about 1.1 ns per entry (one CU, bound by its
+    image gathers: 100 ms at 512^2 x 360) against about 4 us per step, so
+    nnz / 128 keeps the rebuilds near 4% of the chain's time."""
+    return max(int(cfg["resync_every"]), int(nnz) // 128)
 
 
 def _params(P, cfg, n_steps, seed, chain_id, precision="f32", nnz=0):
