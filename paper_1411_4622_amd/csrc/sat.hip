@@ -645,6 +645,8 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
     const bool tk = ps && !r_in_lds && table_lds <= budget && ps->k_glob_tk && tcol_bytes(geom, params) > 0 &&
                     ws_bytes >= need + tcb;
     if (ps && !r_in_lds && !tk && !ps->k_glob) ps = nullptr;
+    // the global mode's slot words hold the angle in 9 bits
+    if (ps && !r_in_lds && geom->n_angles > kSlotMaxAngles) ps = nullptr;
     // rows too long for the pipelined body's registers: the long-row body
     // (one-byte lengths: FP32 only)
     const bool lng = ahead && !ps && long_allowed(geom, csr, params) && !(lenq && params->precision == PILA_F64);
@@ -951,7 +953,7 @@ static int32_t batch_plan(int32_t n_jobs, const sat_job* jobs, const sat_launch*
         const bool ahead = J.proposal == PILA_PROP_CLAMP;
         const bool fits = ahead && waves * kWave <= kPipedThreads;
         const BatchShape* bs = nullptr;
-        if (fits && piped_allowed(jobs[j].geom, jobs[j].csr)) {
+        if (fits && piped_allowed(jobs[j].geom, jobs[j].csr) && jobs[j].geom->n_angles <= kSlotMaxAngles) {
             for (int cpw : {1, 2, 4}) {
                 if (J.m_cand > waves * cpw) continue;
                 for (const BatchShape& sp : batch_shapes(J.precision, J.lenq != 0))

@@ -832,8 +832,14 @@ __device__ __forceinline__ void st32(T* base, uint32_t i, T v)
 
 // Where the residual value of ray g lives in the pipelined body's global
 // mode: the LDS part (angles u < UL, bins k_lo .. k_lo + Kc - 1) as
-// kRaySlotLds | index, else the patch-table slot (2 u + k mod 2) << 13 | k.
+// kRaySlotLds | index, else u << 22 | its position in the tiled global
+// residual (rpos, below 2^22 for U <= 512 and K < 8192).  The patch-table
+// slot of a global entry is 2 u + k mod 2, and k mod 2 is the position's
+// lowest bit, so both come from the word with a few bit operations.
 constexpr int kRaySlotLds = (int)0x80000000;
+constexpr int kSlotPosBits = 22;
+constexpr int32_t kSlotPosMask = (1 << kSlotPosBits) - 1;
+constexpr int kSlotMaxAngles = 512;
 
 __device__ __forceinline__ int32_t ray_slot(const ChainJob& J, int32_t g)
 {
@@ -841,7 +847,13 @@ __device__ __forceinline__ int32_t ray_slot(const ChainJob& J, int32_t g)
     const int k = g - u * J.K;
     const int kk = k - J.k_lo;
     if (u < J.UL && kk >= 0 && kk < J.Kc) return kRaySlotLds | (u * J.Kc + kk);
-    return ((2 * u + (k & 1)) << 13) | k;
+    return (u << kSlotPosBits) | (int32_t)rpos(J, u, k);
+}
+
+// patch-table slot (2 u + k mod 2) of a global entry's slot word
+__device__ __forceinline__ int slot_patch(int32_t tk)
+{
+    return ((tk >> (kSlotPosBits - 1)) & ~1) | (tk & 1);
 }
 
 template <typename Real, int E>
@@ -1010,7 +1022,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     // angle and bin of its slot word or from the ray index
     auto gcol = [&](const RowSet<Real, E>& S, int e) -> uint32_t {
         if (RLDS) return (uint32_t)S.col[e];
-        return kTK ? rpos(J, S.tk[e] >> 14, S.tk[e] & 8191) : rpos_g(J, S.col[e]);
+        return (uint32_t)(S.tk[e] & kSlotPosMask);
     };
     auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
     // residual value at a position of the global residual, or of ray g in LDS
@@ -1044,8 +1056,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             for (int e = 0; e < E; ++e) {
                 const int tk = X.tk[e];
                 if (!(tk & kLdsFlag)) {
-                    const int64_t key = pkey[tk >> 13];
-                    if (key == (((int64_t)(s - 1)) << 13 | (tk & 8191))) X.rv[e] = pval[tk >> 13];
+                    const int ps = slot_patch(tk);
+                    const int64_t key = pkey[ps];
+                    if (key == (((int64_t)(s - 1)) << kSlotPosBits | (tk & kSlotPosMask))) X.rv[e] = pval[ps];
                 }
             }
         }
@@ -1097,8 +1110,9 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                         rl[X.tk[e] & ~kLdsFlag] = rn;
                     } else {
                         st32(r, gcol(X, e), rn);
-                        pkey[X.tk[e] >> 13] = ((int64_t)s << 13) | (X.tk[e] & 8191);
-                        pval[X.tk[e] >> 13] = rn;
+                        const int ps = slot_patch(X.tk[e]);
+                        pkey[ps] = ((int64_t)s << kSlotPosBits) | (X.tk[e] & kSlotPosMask);
+                        pval[ps] = rn;
                     }
                 }
             }

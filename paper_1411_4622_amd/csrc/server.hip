@@ -458,7 +458,8 @@ int32_t cache_get(srv_t* s, const pila_geom* g, PilaEntry** out)
     PILA_TRY(pila_build_with(&e->geom, &e->csr, scratch, kBuildStream));
     // FP32 rows the pipelined body can hold: the slot words of the entries
     // for the server's LDS layout (the same for every chain on this PILA)
-    if (g->len_dtype == PILA_F32 && e->csr.max_row <= 512 && piped_allowed(&e->geom, &e->csr)) {
+    if (g->len_dtype == PILA_F32 && e->csr.max_row <= 512 && g->n_angles <= kSlotMaxAngles &&
+        piped_allowed(&e->geom, &e->csr)) {
         const size_t sizes3[1] = {sizeof(int32_t) * nnz};
         void** dst3[1] = {(void**)&e->tcol};
         PILA_TRY(take(sizes3, dst3, 1));
