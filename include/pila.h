@@ -369,9 +369,14 @@ int32_t sat_drt_run(const pila_geom* geom, const double* d_sino, const sat_param
 
 typedef struct sirt_params {
     int32_t n_iter;
-    int32_t reserved;
-    double lambda; /* relaxation; 1 is the unrelaxed update */
+    int32_t flags;  /* 0, or PILA_SIRT_REUSE_LAYOUT */
+    double lambda;  /* relaxation; 1 is the unrelaxed update */
 } sirt_params;
+
+/* sirt_params.flags: the workspace still holds the factor matrix and both
+ * tile layouts that an earlier sirt_run on the same geometry and PILA built
+ * in it (same workspace, unchanged since); the call skips building them */
+#define PILA_SIRT_REUSE_LAYOUT 1
 
 /* sirt_workspace_size - device workspace bytes that sirt_run needs: the
  * factor matrix, residuals and partial sums, the transposed image and the two
@@ -388,7 +393,12 @@ int32_t sirt_workspace_size(const pila_geom* geom, const sirt_params* params, si
  * over all rays crossing the pixel).  d_image (N*N) in: start, out: result.
  * h_cost (nullable, n_iter doubles) receives Eq. 4 of the image entering
  * each iteration; the call then synchronises.  Both projections run on
- * tile layouts built at the start of the call; a tile whose entries do not
+ * tile layouts built at the start of the call (with W), unless
+ * params->flags holds PILA_SIRT_REUSE_LAYOUT: then the workspace must hold
+ * them from an earlier call on the same geometry and PILA, and a call of
+ * n_iter iterations continues exactly where the earlier one stopped (the
+ * layouts sit at offsets that do not depend on n_iter).  EINVAL for other
+ * flags.  A tile whose entries do not
  * have the two-neighbour shape is summed from the CSR rows instead (the
  * environment variable PILA_SIRT_CSR=1 forces that for every tile, for
  * tests).  Sums are deterministic; their order differs from a row walk, so

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpila.so")
 PILA_OK, PILA_EINVAL, PILA_ENOMEM, PILA_EHIP, PILA_ESIZE = 0, -1, -2, -3, -4
 PILA_ECANCELED, PILA_EBUSY, PILA_ENOTFOUND = -5, -6, -7
 PILA_F64, PILA_F32, PILA_U8 = 0, 1, 2
+PILA_SIRT_REUSE_LAYOUT = 1
 SCHEDULES = {"linear": 0, "exp": 1, "cubic": 2}      # PILA_SCHED_*
 PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
 BODY_PIPED, BODY_LONG, BODY_GENERAL = 1, 2, 3         # PILA_BODY_* kinds
@@ -87,7 +88,7 @@ class CSatLaunch(C.Structure):
 
 
 class CSirtParams(C.Structure):
-    _fields_ = [("n_iter", C.c_int32), ("reserved", C.c_int32), ("lam", C.c_double)]
+    _fields_ = [("n_iter", C.c_int32), ("flags", C.c_int32), ("lam", C.c_double)]
 
 
 class CSirtSeqParams(C.Structure):
@@ -538,13 +539,16 @@ def sat_batch_graph(jobs: List[Job], waves_per_chain: int = 4, chains_per_cu: in
 
 
 def sirt_run(pila: Pila, sino, n_iter: int, lam: float, image, workspace=None,
-             cost: bool = True):
-    """Simultaneous SIRT (Eq. 10-11); image updated in place; returns costs."""
+             cost: bool = True, reuse_layout: bool = False):
+    """Simultaneous SIRT (Eq. 10-11); image updated in place; returns costs.
+    reuse_layout: the workspace holds the layouts of an earlier call on the
+    same PILA (PILA_SIRT_REUSE_LAYOUT)."""
     torch = _torch()
     g = pila.geom
     assert image.dtype == torch.float64 and image.is_cuda and image.is_contiguous()
     assert sino.dtype == torch.float64 and sino.is_cuda and sino.is_contiguous()
-    p = CSirtParams(int(n_iter), 0, float(lam))
+    assert workspace is not None or not reuse_layout, "reuse_layout needs the earlier workspace"
+    p = CSirtParams(int(n_iter), PILA_SIRT_REUSE_LAYOUT if reuse_layout else 0, float(lam))
     lib = load()
     if workspace is None:
         nb = C.c_size_t(0)

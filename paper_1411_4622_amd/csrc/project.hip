@@ -744,7 +744,6 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     L.q = take(sizeof(double) * G);
     const size_t nrt0 = (size_t)g->n_angles * ((g->n_bins + 63) / 64);
     L.partial = take(sizeof(double) * (nrt0 > (size_t)kGatherBlocks ? nrt0 : (size_t)kGatherBlocks));
-    L.sse = take(sizeof(double) * (size_t)(n_iter > 0 ? n_iter : 1));
     L.fT = take(sizeof(double) * NP);
     L.tiles = take(sizeof(int32_t) * (n_tiles ? n_tiles : 1));
     L.flag = take(sizeof(int32_t) * (n_tiles ? n_tiles : 1));
@@ -762,6 +761,8 @@ SirtLayout sirt_layout(const pila_geom* g, int32_t n_iter, size_t n_tiles)
     const int band = ray_band(g->n);
     const size_t n_bands = (size_t)((g->n + band - 1) / band);
     L.bpart = take(sizeof(double) * n_bands * nrt * 64);
+    // last, so that the layouts above sit at the same offsets for any n_iter
+    L.sse = take(sizeof(double) * (size_t)(n_iter > 0 ? n_iter : 1));
     L.total = at;
     return L;
 }
@@ -873,11 +874,13 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     // irregular shape takes), for tests of that path
     const char* env = std::getenv("PILA_SIRT_CSR");
     const bool force_csr = env && env[0] == '1';
+    const bool reuse = (prm->flags & PILA_SIRT_REUSE_LAYOUT) != 0;
     // factor matrix: W_g = sum of squared lengths of ray g over the support
-    ray_gather_kernel<LenT, kW><<<gb, 256, 0, st>>>(G, csr->t_row_ptr, csr->t_col,
-                                                    (const LenT*)csr->t_len, nullptr, nullptr,
-                                                    nullptr, W, nullptr);
-    if (n_tiles > 0) {
+    if (!reuse)
+        ray_gather_kernel<LenT, kW><<<gb, 256, 0, st>>>(G, csr->t_row_ptr, csr->t_col,
+                                                        (const LenT*)csr->t_len, nullptr, nullptr,
+                                                        nullptr, W, nullptr);
+    if (n_tiles > 0 && !reuse) {
         PILA_HIP(hipMemcpyAsync(d_tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
                                 hipMemcpyHostToDevice, st));
         tile_build_kernel<LenT><<<n_tiles, 64, 0, st>>>(N, U, K, d_tiles, csr->row_ptr, csr->col,
@@ -892,9 +895,10 @@ static int32_t sirt_impl(const pila_geom* geom, const pila_csr* csr, const doubl
     int32_t* range = (int32_t*)(ws + L.range);
     double* bpart = (double*)(ws + L.bpart);
     const int band = ray_band(N), n_bands = (N + band - 1) / band;
-    ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
-                                                     (const LenT*)csr->t_len, roff, r0, r1, rbase, range,
-                                                     csr->nnz, aligned16(csr->t_col, csr->t_len), force_csr);
+    if (!reuse)
+        ray_tile_build_kernel<LenT><<<n_rt, 64, 0, st>>>(N, U, K, nkt, csr->trig, csr->t_row_ptr, csr->t_col,
+                                                         (const LenT*)csr->t_len, roff, r0, r1, rbase, range,
+                                                         csr->nnz, aligned16(csr->t_col, csr->t_len), force_csr);
 
     const double scale = prm->lambda / (double)geom->n_angles;
     const dim3 tgrid((unsigned)((N + 31) / 32), (unsigned)((N + 31) / 32));
@@ -931,6 +935,7 @@ extern "C" int32_t sirt_run(const pila_geom* geom, const pila_csr* csr, const do
     if (!params || !d_sino || !d_image) return fail(PILA_EINVAL, "params, sinogram or image is NULL");
     if (!csr->trig) return fail(PILA_EINVAL, "trig (from pila_build) is NULL");
     if (!std::isfinite(params->lambda)) return fail(PILA_EINVAL, "lambda is not finite");
+    if (params->flags & ~PILA_SIRT_REUSE_LAYOUT) return fail(PILA_EINVAL, "unknown flags %d", params->flags);
     size_t need = 0;
     PILA_TRY(sirt_workspace_size(geom, params, &need));
     if (!d_ws || ws_bytes < need)

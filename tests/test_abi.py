@@ -155,6 +155,21 @@ def test_workspace_sizes(P):
     assert lib.sirt_workspace_size(C.byref(g.c), C.byref(sp), C.byref(n)) == P._binding.PILA_EINVAL
 
 
+def test_sirt_unknown_flags_are_einval(P):
+    """Refused before any device work: host-side checks only (the pointers
+    are never dereferenced)."""
+    from paper_1411_4622_amd._binding import CCsr, CSirtParams
+    lib = P.load()
+    g = _geom(P, n=16, U=12, K=23)
+    fake = 256  # non-NULL placeholders
+    csr = CCsr(1, 1, 1, 0, -1, fake, fake, fake, fake, fake, fake, fake, fake)
+    sp = CSirtParams(3, 2, 0.5)
+    rc = lib.sirt_run(C.byref(g.c), C.byref(csr), C.c_void_p(fake), C.byref(sp), C.c_void_p(fake),
+                      C.c_void_p(fake), C.c_size_t(1 << 40), None, None)
+    assert rc == P._binding.PILA_EINVAL
+    assert "flags" in P.last_error()
+
+
 def test_batch_argument_errors(P):
     lib = P.load()
     n = C.c_size_t(0)

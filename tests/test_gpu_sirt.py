@@ -81,3 +81,27 @@ def test_sirt_zero_iterations(P):
     cost = P.sirt_run(pl, torch.zeros(U, K, dtype=torch.float64, device="cuda"), 0, 0.1, img)
     assert len(cost) == 0
     assert torch.all(img == 0.3)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sirt_layout_reuse_continues_exactly(P, dt):
+    """Two calls of 4 iterations, the second reusing the first's workspace
+    layouts (PILA_SIRT_REUSE_LAYOUT), give the bits of one 8-iteration call."""
+    N, U, K = 300, 24, 425  # two image bands in the forward projection
+    ell = datagen.random_ellipses(77, N, 6)
+    sl = datagen.make_slice(N, U, K, ell, masked=True, I0=1e4, noise_seed=8)
+    pl = P.pila_build(P.Geometry(N, sl.angles, K, sl.mask, dt))
+    sino = torch.from_numpy(sl.sino).cuda()
+    one = torch.from_numpy(sl.f0.copy()).cuda()
+    c_one = P.sirt_run(pl, sino, 8, 0.5, one)
+    two = torch.from_numpy(sl.f0.copy()).cuda()
+    nb = P._binding.C.c_size_t(0)
+    p8 = P._binding.CSirtParams(8, 0, 0.5)
+    P._binding._check(P.load().sirt_workspace_size(P._binding.C.byref(pl.geom.c), P._binding.C.byref(p8),
+                                                   P._binding.C.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    c_a = P.sirt_run(pl, sino, 4, 0.5, two, workspace=ws)
+    c_b = P.sirt_run(pl, sino, 4, 0.5, two, workspace=ws, reuse_layout=True)
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    assert np.array_equal(np.concatenate([c_a, c_b]), c_one)
