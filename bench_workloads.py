@@ -211,6 +211,27 @@ def run_c2(args, P, torch, datagen):
     f32_img = img.cpu().numpy()
     rmse32 = datagen.rmse(f32_img, sl.truth)
 
+    # the same chain from a HIP graph captured once (its launch sequence:
+    # one segment per possible resync, the rebuilds and finishes), replayed
+    # on the same buffers; the image must come out with the same bits
+    pl_g = P.pila_build(geom)
+    graph = P.sat_graph(pl_g, sino, prm, img, workspace=ws)
+    graph_ms = []
+    same = True
+    for _ in range(3):
+        img.copy_(f0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        graph.launch()
+        e1.record(stream)
+        e1.synchronize()
+        graph_ms.append(e0.elapsed_time(e1))
+        same = same and bool(np.array_equal(img.cpu().numpy(), f32_img))
+    graph.close()
+    log("graph replay: chain %.1f ms (eager %.1f ms), same image: %s"
+        % (statistics.mean(graph_ms), statistics.mean(kernel_ms), same))
+
     rmse64 = None
     if not args.no_fp64_reference:
         log("fp64 reference chain (same seeds, untimed)")
@@ -285,6 +306,8 @@ def run_c2(args, P, torch, datagen):
                      "avg_launch_ms": 1e3 * launch_s,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "chain_ms_per_step": statistics.mean(kernel_ms)},
+        "graph": {"chain_ms_eager": statistics.mean(kernel_ms), "chain_ms_graph": statistics.mean(graph_ms),
+                  "replays": len(graph_ms), "same_image_bits": same},
         "cpu_baseline": cpu,
         "device": info,
     }
