@@ -93,6 +93,7 @@ struct ChainShared {
     double S[kMaxCand];
     double fn[kMaxCand];
     double d[kMaxCand];
+    int64_t rb[kMaxCand], re[kMaxCand];  // general body: each estimate's row
     int32_t p[kMaxCand];
     double red[kMaxWaves];
     double scalar[4];
@@ -741,18 +742,155 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
     Schedule sched;
     sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
     const bool f32 = sizeof(Real) == 4;
+    const LenT* lenp = (const LenT*)J.len;
+
+    // The wavefront's estimates are m = wave + k NW.  Those with k < KA have
+    // their draws one step ahead: the support lookup is issued at the start
+    // of the step before, the row offsets after that step's sums, so both
+    // loads are in flight while the step runs.  Further estimates (M > KA NW)
+    // are drawn at their step.  Estimates are scored two at a time, their
+    // rows' loads interleaved; each lane still adds each row's entries in
+    // ascending order, so the sums are the canonical ones.
+    constexpr int KA = 2;
+    constexpr int U = 8;  // entries per lane and row in flight
+    const int KM = (M + NW - 1) / NW;
+    int32_t dp[KA];
+    int64_t db[KA], de[KA];
+    double ddel[KA];
+    auto draw = [&](int64_t st, int m, double* delta) -> int32_t {
+        const Words4 w = philox4x64(J.seed, J.chain_id, (uint64_t)st, (uint64_t)m, 0, 0);
+        *delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+        return J.support[__umul64hi(w.w0, (uint64_t)J.P)];
+    };
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const int m = wave + k * NW;
+        dp[k] = 0;
+        db[k] = de[k] = 0;
+        ddel[k] = 0.0;
+        if (m < M && cs.s_begin < cs.n_steps) {
+            dp[k] = draw(cs.s_begin, m, &ddel[k]);
+            db[k] = J.row_ptr[dp[k]];
+            de[k] = J.row_ptr[dp[k] + 1];
+        }
+    }
+    // the value an estimate proposes for pixel p: the change drawn for it,
+    // clamped, or redrawn until in range (Eq. 3)
+    auto propose = [&](int64_t st, int m, int32_t p, double delta, double* fn_out) -> double {
+        const double fo = J.f[p];
+        double fn = fo + delta;
+        if (J.proposal == PILA_PROP_REDRAW) {
+            for (uint64_t j = 1; (fn < J.f_min || fn > J.f_max) && j <= kRedrawMax; ++j) {
+                delta = J.delta_max *
+                        (2.0 * unit53(philox4x64(J.seed, J.chain_id, (uint64_t)st, (uint64_t)m, 0, j).w1) - 1.0);
+                fn = fo + delta;
+            }
+            if (fn < J.f_min || fn > J.f_max) fn = fo;
+        } else {
+            if (fn < J.f_min) fn = J.f_min;
+            if (fn > J.f_max) fn = J.f_max;
+        }
+        *fn_out = fn;
+        return fn - fo;
+    };
 
     for (int64_t s = cs.s_begin; s < cs.n_steps; ++s) {
         const double T = sched.at(s, cs.n_steps, J.n_stages);
-        for (int m = wave; m < M; m += NW) {
-            int32_t p;
-            double fn, d;
-            const Real S = estimate_sum<Real, !LDS, LenT>(J, r, (uint64_t)s, (uint64_t)m, 0, lane, &p, &fn, &d);
-            if (lane == 0) {
-                sh.S[m] = (double)S;
-                sh.p[m] = p;
-                sh.fn[m] = fn;
-                sh.d[m] = d;
+        // next step's support lookups, in flight during this step
+        int32_t np[KA];
+        double ndel[KA];
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const int m = wave + k * NW;
+            np[k] = 0;
+            ndel[k] = 0.0;
+            if (m < M && s + 1 < cs.n_steps) np[k] = draw(s + 1, m, &ndel[k]);
+        }
+        for (int k0 = 0; k0 < KM; k0 += 2) {
+            int32_t pp[2];
+            int64_t bb[2], ee[2];
+            double fnn[2], dd[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = k0 + h, m = wave + k * NW;
+                pp[h] = 0;
+                bb[h] = ee[h] = 0;
+                fnn[h] = dd[h] = 0.0;
+                if (m < M) {
+                    double delta;
+                    if (k < KA) {
+                        pp[h] = k == 0 ? dp[0] : dp[1];
+                        bb[h] = k == 0 ? db[0] : db[1];
+                        ee[h] = k == 0 ? de[0] : de[1];
+                        delta = k == 0 ? ddel[0] : ddel[1];
+                    } else {
+                        pp[h] = draw(s, m, &delta);
+                        bb[h] = J.row_ptr[pp[h]];
+                        ee[h] = J.row_ptr[pp[h] + 1];
+                    }
+                    dd[h] = propose(s, m, pp[h], delta, &fnn[h]);
+                }
+            }
+            const Real dra = (Real)dd[0], drb = (Real)dd[1];
+            const int64_t la = ee[0] - bb[0], lb = ee[1] - bb[1];
+            const int64_t lmax = la > lb ? la : lb;
+            Real acca = 0, accb = 0;
+            for (int64_t o = lane; o < lmax; o += (int64_t)kWave * U) {
+                int32_t ca[U], cb[U];
+                Real la_[U], lb_[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    const int64_t qa = bb[0] + (o + c * kWave < la ? o + c * kWave : 0);
+                    const int64_t qb = bb[1] + (o + c * kWave < lb ? o + c * kWave : 0);
+                    ca[c] = J.col[qa];
+                    la_[c] = (Real)lenp[qa];
+                    cb[c] = J.col[qb];
+                    lb_[c] = (Real)lenp[qb];
+                }
+                Real ra[U], rb[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    ra[c] = r[ridx<!LDS>(J, ca[c])];
+                    rb[c] = r[ridx<!LDS>(J, cb[c])];
+                }
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    if (o + c * kWave < la) {
+                        const Real t = dra * la_[c];
+                        acca = fma(t, (Real)2 * ra[c] + t, acca);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    if (o + c * kWave < lb) {
+                        const Real t = drb * lb_[c];
+                        accb = fma(t, (Real)2 * rb[c] + t, accb);
+                    }
+                }
+            }
+            const Real Sa = wave_canon_sum(acca), Sb = wave_canon_sum(accb);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int m = wave + (k0 + h) * NW;
+                if (lane == 0 && m < M) {
+                    sh.S[m] = (double)(h == 0 ? Sa : Sb);
+                    sh.p[m] = pp[h];
+                    sh.fn[m] = fnn[h];
+                    sh.d[m] = dd[h];
+                    sh.rb[m] = bb[h];
+                    sh.re[m] = ee[h];
+                }
+            }
+        }
+        // next step's row offsets, in flight during the decision and scatter
+#pragma unroll
+        for (int k = 0; k < KA; ++k) {
+            const int m = wave + k * NW;
+            if (m < M && s + 1 < cs.n_steps) {
+                dp[k] = np[k];
+                ddel[k] = ndel[k];
+                db[k] = J.row_ptr[np[k]];
+                de[k] = J.row_ptr[np[k] + 1];
             }
         }
         const double co = sqrt(cs.sse / KU);
@@ -762,33 +900,17 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
         __syncthreads();
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, N1, lnN1);
         const double d_star = uniform_f64(sh.d[dn.ms]);
-        if (dn.accept && wave == dn.ms % NW) {  // the owner of the winner applies Eq. 6
-            const int32_t p = sh.p[dn.ms];
-            const LenT* len = (const LenT*)J.len;
-            const int64_t b = J.row_ptr[p], e = J.row_ptr[p + 1];
+        // Eq. 6 for the winner, by the whole workgroup (one entry per thread;
+        // the row's rays are distinct, so no two threads touch one value); an
+        // accepted zero change leaves image and residual as they are
+        if (dn.accept && d_star != 0.0) {
+            const int64_t b = sh.rb[dn.ms], e = sh.re[dn.ms];
             const Real dr = (Real)d_star;
-            // U entries per lane loaded before any is written (the row's rays
-            // are distinct, so no write changes a value read here)
-            constexpr int U = 4;
-            for (int64_t q0 = b + lane; q0 < e; q0 += (int64_t)kWave * U) {
-                int32_t cc[U];
-                Real ll[U], rr[U];
-#pragma unroll
-                for (int c = 0; c < U; ++c) {
-                    const int64_t q = q0 + (int64_t)c * kWave < e ? q0 + (int64_t)c * kWave : b;
-                    cc[c] = J.col[q];
-                    ll[c] = (Real)len[q];
-                }
-                uint32_t at[U];
-#pragma unroll
-                for (int c = 0; c < U; ++c) at[c] = ridx<!LDS>(J, cc[c]);
-#pragma unroll
-                for (int c = 0; c < U; ++c) rr[c] = r[at[c]];
-#pragma unroll
-                for (int c = 0; c < U; ++c)
-                    if (q0 + (int64_t)c * kWave < e) r[at[c]] = rr[c] + dr * ll[c];
+            for (int64_t q = b + threadIdx.x; q < e; q += blockDim.x) {
+                const uint32_t at = ridx<!LDS>(J, J.col[q]);
+                r[at] = r[at] + dr * (Real)lenp[q];
             }
-            if (lane == 0) J.f[p] = sh.fn[dn.ms];
+            if (threadIdx.x == 0) J.f[sh.p[dn.ms]] = sh.fn[dn.ms];
         }
         count_decision(J, cs, dn, d_star, s);
         if (f32 && J.resync_every > 0 && cs.since >= J.resync_every) {
