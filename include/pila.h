@@ -47,6 +47,7 @@ extern "C" {
 #define PILA_ECANCELED (-5) /* request cancelled */
 #define PILA_EBUSY (-6)     /* not admissible now; retry later */
 #define PILA_ENOTFOUND (-7) /* unknown ticket */
+#define PILA_ETIMEDOUT (-8) /* the workgroups of a split chain did not all run at once */
 
 /* storage / arithmetic types */
 #define PILA_F64 0
@@ -71,6 +72,7 @@ extern "C" {
 #define PILA_BODY_PIPED 1     /* rows in registers, estimates drawn ahead */
 #define PILA_BODY_LONG 2      /* rows of more than 512 entries, one estimate per wavefront */
 #define PILA_BODY_GENERAL 3   /* any row length and M, draws at the step (needed for redraw) */
+#define PILA_BODY_SPLIT 4     /* one chain over several workgroups (their count in bits 8..15) */
 #define PILA_BODY_GLOBAL_R 16 /* flag: the residual lives (partly) in global memory */
 #define PILA_BODY_SEGMENTED 32 /* flag: FP32 resyncs ran grid-wide between launches */
 
@@ -184,7 +186,8 @@ typedef struct sat_params {
 typedef struct sat_stats {
     int64_t steps, accepts, accepts_nonzero;
     int32_t resyncs;
-    int32_t status;         /* PILA_OK, or PILA_EINVAL when Eq. 8 failed */
+    int32_t status;         /* PILA_OK, PILA_EINVAL when Eq. 8 failed, or
+                               PILA_ETIMEDOUT (split chains, below) */
     double T0_used, TN_used;
     double sse_final;       /* running sum of squared residuals at the end */
     double cost_final;      /* Eq. 4 of the final image (running value) */
@@ -209,7 +212,10 @@ typedef struct sat_trace {
 } sat_trace;
 
 /*
- * sat_workspace_size - device workspace bytes that sat_run needs.
+ * sat_workspace_size - device workspace bytes that sat_run needs: the chain
+ * state, plus room for the slot words of the pipelined body or for the
+ * copies of a split chain (below).  A workspace of at least the chain state
+ * is accepted; the extra room only selects the faster bodies.
  */
 int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes);
 
@@ -236,6 +242,16 @@ int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size
  * synchronises.  trace (nullable, host struct of device arrays) records
  * every step.  Errors: EINVAL (bad sizes/params, dtype mismatch, empty
  * support), ENOMEM (ws_bytes below sat_workspace_size), EHIP.
+ * Split chains (PILA_BODY_SPLIT): when the residual does not fit in LDS,
+ * m_cand >= 4 and m_cand * max_row >= 16384, and the workspace has room
+ * for min(8, m_cand) - 1 copies of the residual and the image, the chain
+ * runs on min(8, m_cand) workgroups, each scoring its share of the
+ * estimates on its own copies and exchanging the sums through the
+ * workspace every step (same results as one workgroup).  The workgroups
+ * must run at the same time: a workgroup that waits longer than 10 s for
+ * the others (PILA_SPLIT_WAIT_MS in the environment, in ms, changes the
+ * limit) ends the chain with stats.status = PILA_ETIMEDOUT, the image
+ * holding the state it had reached.
  */
 int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino,
                 const sat_params* params, double* d_image, void* d_ws, size_t ws_bytes,

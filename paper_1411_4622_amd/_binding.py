@@ -18,12 +18,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpila.so")
 
 PILA_OK, PILA_EINVAL, PILA_ENOMEM, PILA_EHIP, PILA_ESIZE = 0, -1, -2, -3, -4
-PILA_ECANCELED, PILA_EBUSY, PILA_ENOTFOUND = -5, -6, -7
+PILA_ECANCELED, PILA_EBUSY, PILA_ENOTFOUND, PILA_ETIMEDOUT = -5, -6, -7, -8
 PILA_F64, PILA_F32, PILA_U8 = 0, 1, 2
 PILA_SIRT_REUSE_LAYOUT = 1
 SCHEDULES = {"linear": 0, "exp": 1, "cubic": 2}      # PILA_SCHED_*
 PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
-BODY_PIPED, BODY_LONG, BODY_GENERAL = 1, 2, 3         # PILA_BODY_* kinds
+BODY_PIPED, BODY_LONG, BODY_GENERAL, BODY_SPLIT = 1, 2, 3, 4  # PILA_BODY_* kinds
 BODY_GLOBAL_R, BODY_SEGMENTED = 16, 32                # PILA_BODY_* flags
 
 EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run", "sat_run_static",

@@ -2,6 +2,7 @@
 // entry points sat_run / sat_run_batch.  The chain bodies and their
 // algorithm are in sat_chain.hpp.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <memory>
 #include <mutex>
@@ -249,6 +250,51 @@ __global__ __launch_bounds__(1024) void sat_simple_kernel(ChainJob job, int lds_
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     run_chain_simple_dispatch<Real, LenT>(job, lds, lds_bytes, sh);
+}
+
+// at most 8 wavefronts per workgroup of a split chain (256 registers per lane)
+constexpr int kSplitThreads = 512;
+
+// one segment of a chain split over gridDim.x workgroups; workgroup g > 0
+// works on its own copies of the residual and the image
+template <typename Real, typename LenT = Real>
+__global__ __launch_bounds__(kSplitThreads) void sat_split_kernel(ChainJob job, SplitX X)
+{
+    __shared__ SplitShared sp;
+    if (job.carry->done || job.carry->status != PILA_OK) return;
+    const int g = blockIdx.x;
+    if (g > 0) {
+        char* base = X.copies + (int64_t)(g - 1) * (X.r_bytes + X.f_bytes);
+        job.r = base;
+        job.f = (double*)(base + X.r_bytes);
+        job.tr_m = nullptr;
+        job.tr_acc = nullptr;
+        job.tr_dc = nullptr;
+        job.stats = nullptr;
+    }
+    run_chain_split<Real, LenT>(job, X, g, sp);
+}
+
+// A split chain's copies: at the start (start = 1) the residual and the
+// image, with the exchange words cleared; after a resync (start = 0, only
+// when the segment asked for one) the residual.
+__global__ __launch_bounds__(256) void sat_split_copy_kernel(ChainJob job, SplitX X, int64_t n_image, int start)
+{
+    if (!start && !job.carry->resync_due) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    if (start && tid < 2 * kMaxCand * 2) X.word[tid] = 0;
+    const int64_t nr = X.r_bytes / 16;
+    const uint4* rs = (const uint4*)job.r;
+    for (int k = 1; k < X.groups; ++k) {
+        char* base = X.copies + (int64_t)(k - 1) * (X.r_bytes + X.f_bytes);
+        uint4* rd = (uint4*)base;
+        for (int64_t i = tid; i < nr; i += nt) rd[i] = rs[i];
+        if (start) {
+            double* fd = (double*)(base + X.r_bytes);
+            for (int64_t i = tid; i < n_image; i += nt) fd[i] = job.f[i];
+        }
+    }
 }
 
 // Grid-wide FP64 rebuild of a chain's residual, one wavefront per 64-ray
@@ -553,6 +599,59 @@ struct LaunchTimer {
     }
 };
 
+// A chain split over kSplitGroups workgroups (run_chain_split) when its
+// residual lives in global memory and a step scores at least
+// kSplitMinEntries row entries (M times the longest row): below that one
+// compute unit's gathers take less time than the exchange of the sums.
+constexpr int kSplitGroups = 8;
+constexpr int kSplitMinM = 4;
+// how long (ms) a workgroup of a split chain waits for the others' sums
+constexpr int64_t kSplitWaitMs = 10000;
+constexpr int64_t kSplitMinEntries = 16384;
+constexpr size_t kSplitWordBytes = 2 * kMaxCand * 2 * sizeof(unsigned long long);
+
+bool split_wanted(const pila_csr* c, const sat_params* p)
+{
+    return p->m_cand >= kSplitMinM && (int64_t)p->m_cand * c->max_row >= kSplitMinEntries;
+}
+
+// the exchange words, then per workgroup after the first a residual copy
+// and an image copy
+size_t split_bytes(const pila_geom* g, const sat_params* p)
+{
+    const size_t rs = p->precision == PILA_F32 ? 4 : 8;
+    return align256(kSplitWordBytes) + (size_t)(kSplitGroups - 1) * (align256(rs * residual_values(g)) +
+                                                                     align256(8 * (size_t)g->n * g->n));
+}
+
+// the launches of a split chain: initial rebuild, Eq. 8 and the copies, then
+// one segment per resync (rebuilt grid-wide on group 0's residual and copied
+// to the others), then the statistics
+template <typename Real, typename LenT>
+int32_t enqueue_split(ChainJob& J, SplitX& X, int nw, int64_t n_image, int64_t n_seg, bool resync, unsigned rb,
+                      hipStream_t st, LaunchTimer* tm)
+{
+    const unsigned cb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((X.r_bytes / 16 + 255) / 256, 2048));
+    sat_rebuild_kernel<Real, LenT><<<rb, 256, 0, st>>>(J, 0);
+    sat_setup_kernel<Real, LenT><<<1, kPipedThreads, 0, st>>>(J);
+    sat_split_copy_kernel<<<cb, 256, 0, st>>>(J, X, n_image, 1);
+    for (int64_t k = 0; k < n_seg; ++k) {
+        void* args[] = {&J, (void*)&X};
+        PILA_TRY(tm->mark(st));
+        PILA_HIP(hipLaunchKernel((const void*)sat_split_kernel<Real, LenT>, dim3(X.groups), dim3(nw * kWave), args,
+                                 0, st));
+        PILA_TRY(tm->mark(st));
+        if (resync) {
+            sat_rebuild_kernel<Real, LenT><<<rb, 256, 0, st>>>(J, 1);
+            sat_split_copy_kernel<<<cb, 256, 0, st>>>(J, X, n_image, 0);
+            sat_resync_finish_kernel<<<1, 64, 0, st>>>(J);
+        }
+    }
+    sat_final_kernel<<<1, 1, 0, st>>>(J);
+    PILA_HIP(hipGetLastError());
+    return PILA_OK;
+}
+
 int32_t launch1(ChainKernel k, ChainJob* J, int threads, int lds, hipStream_t st, LaunchTimer* tm)
 {
     PILA_TRY(set_lds((const void*)k, lds));
@@ -597,7 +696,11 @@ extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* p
     clear_error();
     PILA_TRY(check_geom(geom));
     if (!params || !bytes) return fail(PILA_EINVAL, "params or bytes is NULL");
-    *bytes = chain_bytes(geom, params) + tcol_bytes(geom, params);
+    // room for a split chain's copies wherever the residual may not fit in
+    // LDS (it always does below 64 KB)
+    const size_t rv = (size_t)geom->n_angles * geom->n_bins * (params->precision == PILA_F32 ? 4 : 8);
+    const size_t sb = params->m_cand >= kSplitMinM && rv > 65536 ? split_bytes(geom, params) : 0;
+    *bytes = chain_bytes(geom, params) + std::max(tcol_bytes(geom, params), sb);
     return PILA_OK;
 }
 
@@ -658,10 +761,45 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
                 J, csr->nnz, (int32_t*)((char*)d_ws + need));
     }
     const bool long_seg = lng && !r_in_lds && resync;
-    const bool simple_seg = !ps && !lng && !r_in_lds && resync;
+    // long rows and many estimates with the residual in global memory: the
+    // chain split over several workgroups, when the workspace has room for
+    // their copies after the chain state
+    const bool split = !ps && !lng && !r_in_lds && split_wanted(csr, params) &&
+                       !(lenq && params->precision == PILA_F64) && ws_bytes >= need + split_bytes(geom, params) &&
+                       ((uintptr_t)d_ws & 255) == 0;
+    const bool simple_seg = !ps && !lng && !r_in_lds && resync && !split;
     const int glob = r_in_lds ? 0 : PILA_BODY_GLOBAL_R;
     int body = 0;
-    if (piped_seg || long_seg || simple_seg) {
+    if (split) {
+        const int M = params->m_cand;
+        const int ng = std::min(kSplitGroups, M);
+        const int nw = std::min(kSplitThreads / kWave, (M + ng - 1) / ng);
+        SplitX X;
+        X.word = (unsigned long long*)((char*)d_ws + need);
+        X.copies = (char*)d_ws + need + align256(kSplitWordBytes);
+        X.r_bytes = (int64_t)align256((size_t)rs * residual_values(geom));
+        X.f_bytes = (int64_t)align256(8 * (size_t)geom->n * geom->n);
+        X.groups = ng;
+        X.pad = 0;
+        int khz = 0;
+        int dev = 0;
+        PILA_HIP(hipGetDevice(&dev));
+        PILA_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        // PILA_SPLIT_WAIT_MS (environment) shortens or lengthens the wait
+        int64_t wait_ms = kSplitWaitMs;
+        if (const char* e = std::getenv("PILA_SPLIT_WAIT_MS")) wait_ms = std::max<int64_t>(0, std::atoll(e));
+        X.wait_ticks = (int64_t)(khz > 0 ? khz : 100000) * wait_ms;
+        body = PILA_BODY_SPLIT | PILA_BODY_GLOBAL_R | PILA_BODY_SEGMENTED | (ng << 8);
+        const int T = (int)((G + 63) / 64);
+        const unsigned rb = (unsigned)std::min<int64_t>((T + 3) / 4, 4096);
+        const int64_t n_seg = resync ? params->n_steps / params->resync_every + 1 : 1;
+        const int64_t n_image = (int64_t)geom->n * geom->n;
+        const int32_t rc = params->precision == PILA_F64
+                               ? enqueue_split<double, double>(J, X, nw, n_image, n_seg, false, rb, st, &tm)
+                           : lenq ? enqueue_split<float, LenQ>(J, X, nw, n_image, n_seg, resync, rb, st, &tm)
+                                  : enqueue_split<float, float>(J, X, nw, n_image, n_seg, resync, rb, st, &tm);
+        PILA_TRY(rc);
+    } else if (piped_seg || long_seg || simple_seg) {
         body = (piped_seg ? PILA_BODY_PIPED | (ps->cpw << 8) | (ps->e << 16)
                           : long_seg ? PILA_BODY_LONG : PILA_BODY_GENERAL) |
                PILA_BODY_GLOBAL_R | PILA_BODY_SEGMENTED;

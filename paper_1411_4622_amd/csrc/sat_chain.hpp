@@ -270,6 +270,12 @@ __device__ __forceinline__ double uniform_f64(double v)
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // ---------------------------------------------------------------------------
 // Layout of a residual held in global memory: tiles of 4 angles x 8 bins
@@ -933,6 +939,249 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
         return;
     }
     write_stats(J, cs);
+}
+
+// ---------------------------------------------------------------------------
+// split: one chain over G workgroups (one compute unit each).  With long rows
+// and many estimates a step gathers tens of thousands of residual values,
+// one address per lane, and one CU's texture path (one divergent address per
+// clock) bounds it; G workgroups each score M / G of the estimates.
+//
+// Workgroup g scores the estimates m with m mod G == g against its own copy
+// of the residual and of the image (group 0 holds the chain's own arrays)
+// and publishes each sum; every workgroup then holds all M sums, takes the
+// same BoME / Metropolis decision (the same arithmetic on the same values)
+// and applies an accepted change to its own copies, so the copies stay equal
+// bit for bit and no residual or image value crosses between compute units.
+//
+// A sum travels as two 64-bit words, each holding a step stamp in its upper
+// half and one half of the sum's bits in its lower half, stored and polled
+// with relaxed device-scope atomics: each word says by itself which step it
+// belongs to, so the two words need no ordering between them.  The words
+// are double-buffered by step parity; a workgroup is never more than one
+// step ahead of another (it needs the other's sums of the step before), so
+// the buffer it writes holds no sums another workgroup still waits for.
+// Every wait is bounded by the wall clock: a workgroup that gives up ends the
+// chain with PILA_ETIMEDOUT (the others then give up on it in turn).
+//
+// The estimates' pixels, changes and row offsets do not depend on the chain
+// state: wavefront 0 draws all M of them one step ahead (one lane each), the
+// image value with them, patched when the step in between changes that
+// pixel, so the scoring wavefronts read them from LDS.  Sums are the
+// canonical ones (one wavefront per estimate, U entries per lane in flight).
+// The chain state comes from the carry (segments end at FP32 resyncs, which
+// run grid-wide on group 0's copy and are then copied to the others).
+// ---------------------------------------------------------------------------
+struct SplitX {
+    unsigned long long* word;  // [2 parities][kMaxCand][2 halves]
+    char* copies;              // groups 1 .. G-1: residual copy (r_bytes), then image copy (f_bytes)
+    int64_t r_bytes, f_bytes;
+    int64_t wait_ticks;        // wall-clock ticks (pila_device_info.wallclock_khz) a wait may last
+    int32_t groups, pad;
+};
+
+struct SplitShared {
+    ChainShared c;
+    int64_t rb[2][kMaxCand], re[2][kMaxCand];
+    double fn[2][kMaxCand], d[2][kMaxCand];
+    int32_t p[2][kMaxCand];
+    int32_t fail;
+};
+
+// stamp of step s in a word: 1 .. 2^31, never the 0 of a cleared word, and
+// steps two apart (one parity buffer) always differ
+__device__ __forceinline__ uint64_t split_stamp(int64_t s)
+{
+    return (uint64_t)((s & 0x7fffffff) + 1) << 32;
+}
+
+__device__ __forceinline__ unsigned long long* split_word(const SplitX& X, int64_t s, int m)
+{
+    return X.word + ((size_t)(s & 1) * kMaxCand + (size_t)m) * 2;
+}
+
+__device__ __forceinline__ void split_publish(const SplitX& X, int64_t s, int m, double S)
+{
+    const uint64_t bits = (uint64_t)__double_as_longlong(S), st = split_stamp(s);
+    unsigned long long* w = split_word(X, s, m);
+    __hip_atomic_store(w, st | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(w + 1, st | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename Real, typename LenT = Real>
+__device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, SplitShared& sp)
+{
+    ChainShared& sh = sp.c;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6, NW = blockDim.x >> 6;
+    const int G = X.groups;
+    const double KU = (double)J.K * (double)J.U;
+    const int M = J.m_cand;
+    Real* r = (Real*)J.r;
+    const LenT* lenp = (const LenT*)J.len;
+    const bool f32 = sizeof(Real) == 4;
+    ChainState cs = load_carry(J);
+    Schedule sched;
+    sched.start(cs.s_begin, cs.n_steps, J.n_stages, cs.T0, cs.TN, J.schedule);
+
+    auto draw = [&](int64_t st, int m, double* delta) -> int32_t {
+        const Words4 w = philox4x64(J.seed, J.chain_id, (uint64_t)st, (uint64_t)m, 0, 0);
+        *delta = J.delta_max * (2.0 * unit53(w.w1) - 1.0);
+        return J.support[__umul64hi(w.w0, (uint64_t)J.P)];
+    };
+    // the value estimate m proposes at step st for a pixel now holding fo:
+    // the drawn change clamped, or redrawn until in range (Eq. 3)
+    auto propose = [&](int64_t st, int m, double fo, double delta) -> double {
+        double fn = fo + delta;
+        if (J.proposal == PILA_PROP_REDRAW) {
+            for (uint64_t j = 1; (fn < J.f_min || fn > J.f_max) && j <= kRedrawMax; ++j) {
+                delta = J.delta_max *
+                        (2.0 * unit53(philox4x64(J.seed, J.chain_id, (uint64_t)st, (uint64_t)m, 0, j).w1) - 1.0);
+                fn = fo + delta;
+            }
+            if (fn < J.f_min || fn > J.f_max) fn = fo;
+        } else {
+            if (fn < J.f_min) fn = J.f_min;
+            if (fn > J.f_max) fn = J.f_max;
+        }
+        return fn;
+    };
+    // wavefront 0, lane m: estimate m of step st into LDS buffer st mod 2
+    const bool book = wave == 0 && lane < M;
+    if (book && cs.s_begin < cs.n_steps) {
+        const int64_t st = cs.s_begin;
+        double delta;
+        const int32_t p = draw(st, lane, &delta);
+        const double fo = J.f[p];
+        const double fn = propose(st, lane, fo, delta);
+        const int b = (int)(st & 1);
+        sp.p[b][lane] = p;
+        sp.fn[b][lane] = fn;
+        sp.d[b][lane] = fn - fo;
+        sp.rb[b][lane] = J.row_ptr[p];
+        sp.re[b][lane] = J.row_ptr[p + 1];
+    }
+    if (threadIdx.x == 0) sp.fail = 0;
+    __syncthreads();
+
+    constexpr int U = 16;  // entries per lane in flight
+    for (int64_t s = cs.s_begin; s < cs.n_steps; ++s) {
+        const int pb = (int)(s & 1);
+        const double T = sched.at(s, cs.n_steps, J.n_stages);
+        const bool more = s + 1 < cs.n_steps;
+        // step s + 1's draws; the support lookups are in flight while this
+        // step's rows are scored
+        int32_t np = 0;
+        double ndel = 0.0;
+        if (book && more) np = draw(s + 1, lane, &ndel);
+        // this workgroup's estimates, one wavefront each
+        for (int j = wave;; j += NW) {
+            const int m = g + G * j;
+            if (m >= M) break;
+            const int64_t b = uniform_i64(sp.rb[pb][m]), len = uniform_i64(sp.re[pb][m]) - b;
+            const Real dr = (Real)uniform_f64(sp.d[pb][m]);
+            Real acc = 0;
+            for (int64_t o = lane; o < len; o += (int64_t)kWave * U) {
+                int32_t cc[U];
+                Real ll[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    const int64_t q = b + (o + c * kWave < len ? o + c * kWave : 0);
+                    cc[c] = J.col[q];
+                    ll[c] = (Real)lenp[q];
+                }
+                Real rr[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) rr[c] = r[rpos_g(J, cc[c])];
+#pragma unroll
+                for (int c = 0; c < U; ++c) {
+                    if (o + c * kWave < len) {
+                        const Real t = dr * ll[c];
+                        acc = fma(t, (Real)2 * rr[c] + t, acc);
+                    }
+                }
+            }
+            const double S = (double)wave_canon_sum(acc);
+            if (lane == 0) {
+                sh.S[m] = S;
+                split_publish(X, s, m, S);
+            }
+        }
+        // step s + 1's row offsets and image values, in flight during the
+        // exchange; then the other workgroups' sums
+        int64_t nb = 0, ne = 0;
+        double nfo = 0.0;
+        if (book && more) {
+            nb = J.row_ptr[np];
+            ne = J.row_ptr[np + 1];
+            nfo = J.f[np];
+        }
+        if (wave == 0) {
+            bool need = lane < M && lane % G != g;
+            const uint64_t want = split_stamp(s);
+            const uint64_t t0 = wall_clock64();
+            while (__ballot(need) != 0) {
+                if (need) {
+                    unsigned long long* w = split_word(X, s, lane);
+                    const uint64_t hi = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t lo = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((hi & ~0xffffffffull) == want && (lo & ~0xffffffffull) == want) {
+                        sh.S[lane] = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+                        need = false;
+                    }
+                }
+                if ((int64_t)(wall_clock64() - t0) > X.wait_ticks) {
+                    if (lane == 0) sp.fail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        const double co = sqrt(cs.sse / KU);
+        const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+        const double lnN1 = log(N1), invT = 1.0 / T;
+        __syncthreads();
+        if (sp.fail) {
+            cs.status = PILA_ETIMEDOUT;
+            cs.n_steps = 0;
+            break;
+        }
+        const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, N1, lnN1);
+        const double d_star = uniform_f64(sp.d[pb][dn.ms]);
+        const bool change = dn.accept && d_star != 0.0;
+        int32_t pstar = 0;
+        double fnstar = 0.0;
+        // Eq. 6 on this workgroup's copies (one entry per thread)
+        if (change) {
+            const int64_t b = uniform_i64(sp.rb[pb][dn.ms]), e = uniform_i64(sp.re[pb][dn.ms]);
+            const Real dr = (Real)d_star;
+            for (int64_t q = b + threadIdx.x; q < e; q += blockDim.x) {
+                const uint32_t at = rpos_g(J, J.col[q]);
+                r[at] = r[at] + dr * (Real)lenp[q];
+            }
+            pstar = uniform_i32(sp.p[pb][dn.ms]);
+            fnstar = uniform_f64(sp.fn[pb][dn.ms]);
+            if (threadIdx.x == 0) J.f[pstar] = fnstar;
+        }
+        count_decision(J, cs, dn, d_star, s);
+        // step s + 1's estimates: the image value read before this step's
+        // change, patched with it
+        if (book && more) {
+            const double fo = change && np == pstar ? fnstar : nfo;
+            const double fn = propose(s + 1, lane, fo, ndel);
+            sp.p[pb ^ 1][lane] = np;
+            sp.fn[pb ^ 1][lane] = fn;
+            sp.d[pb ^ 1][lane] = fn - fo;
+            sp.rb[pb ^ 1][lane] = nb;
+            sp.re[pb ^ 1][lane] = ne;
+        }
+        if (f32 && J.resync_every > 0 && cs.since >= J.resync_every) {
+            __syncthreads();
+            if (g == 0) save_carry(J, cs, s + 1, true);
+            return;
+        }
+        __syncthreads();
+    }
+    if (g == 0) save_carry(J, cs, cs.n_steps, false);
 }
 
 // ---------------------------------------------------------------------------
