@@ -243,9 +243,9 @@ int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size
  * every step.  Errors: EINVAL (bad sizes/params, dtype mismatch, empty
  * support), ENOMEM (ws_bytes below sat_workspace_size), EHIP.
  * Split chains (PILA_BODY_SPLIT): when the residual does not fit in LDS,
- * m_cand >= 4 and m_cand * max_row >= 16384, and the workspace has room
- * for min(8, m_cand) - 1 copies of the residual and the image, the chain
- * runs on min(8, m_cand) workgroups, each scoring its share of the
+ * m_cand >= 4 and m_cand * (nnz / n_support) >= 12288, and the workspace
+ * has room for 15 copies of the residual and the image, the chain runs on
+ * G = m_cand / 4 workgroups (at least 2, at most 16), each scoring its share of the
  * estimates on its own copies and exchanging the sums through the
  * workspace every step (same results as one workgroup).  The workgroups
  * must run at the same time: a workgroup that waits longer than 10 s for

@@ -599,20 +599,29 @@ struct LaunchTimer {
     }
 };
 
-// A chain split over kSplitGroups workgroups (run_chain_split) when its
-// residual lives in global memory and a step scores at least
-// kSplitMinEntries row entries (M times the longest row): below that one
-// compute unit's gathers take less time than the exchange of the sums.
-constexpr int kSplitGroups = 8;
+// A chain split over several workgroups (run_chain_split) when its residual
+// lives in global memory and a step scores at least kSplitMinEntries row
+// entries (M times the mean row): below that one compute unit's gathers
+// take less time than the exchange of the sums.  Four estimates per
+// workgroup (M / 4 workgroups, 2 to kSplitGroups) measured best at 1024^2 x
+// 720 for M = 16, 32 and 64 (two per workgroup: more exchange per step,
+// eight: more gathers per compute unit).
+constexpr int kSplitGroups = 16;
 constexpr int kSplitMinM = 4;
 // how long (ms) a workgroup of a split chain waits for the others' sums
 constexpr int64_t kSplitWaitMs = 10000;
-constexpr int64_t kSplitMinEntries = 16384;
+constexpr int64_t kSplitMinEntries = 12288;
 constexpr size_t kSplitWordBytes = 2 * kMaxCand * 2 * sizeof(unsigned long long);
 
 bool split_wanted(const pila_csr* c, const sat_params* p)
 {
-    return p->m_cand >= kSplitMinM && (int64_t)p->m_cand * c->max_row >= kSplitMinEntries;
+    return p->m_cand >= kSplitMinM && c->n_support > 0 &&
+           (int64_t)p->m_cand * (c->nnz / c->n_support) >= kSplitMinEntries;
+}
+
+int split_groups(int m_cand)
+{
+    return std::max(2, std::min(kSplitGroups, m_cand / 4));
 }
 
 // the exchange words, then per workgroup after the first a residual copy
@@ -772,7 +781,7 @@ static int32_t sat_run_impl(const pila_geom* geom, const pila_csr* csr, const do
     int body = 0;
     if (split) {
         const int M = params->m_cand;
-        const int ng = std::min(kSplitGroups, M);
+        const int ng = split_groups(M);
         const int nw = std::min(kSplitThreads / kWave, (M + ng - 1) / ng);
         SplitX X;
         X.word = (unsigned long long*)((char*)d_ws + need);

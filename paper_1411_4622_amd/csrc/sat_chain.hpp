@@ -1063,7 +1063,26 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
     if (threadIdx.x == 0) sp.fail = 0;
     __syncthreads();
 
-    constexpr int U = 16;  // entries per lane in flight
+    // Each wavefront's first estimate of a step has the first U entries per
+    // lane of its row (indices and lengths) loaded during the step before,
+    // while that step's change is applied; further chunks and estimates are
+    // read at the step.
+    constexpr int U = 16;
+    const int m1 = g + G * wave;  // the wavefront's first estimate
+    auto row_chunk = [&](int64_t b, int64_t len, int32_t* cc, Real* ll) {
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            const int64_t q = lane + c * kWave < len ? b + lane + c * kWave : 0;
+            cc[c] = J.col[q];
+            ll[c] = (Real)lenp[q];
+        }
+    };
+    int32_t pc[U];
+    Real pl[U];
+    if (m1 < M && cs.s_begin < cs.n_steps) {
+        const int64_t rb = uniform_i64(sp.rb[cs.s_begin & 1][m1]);
+        row_chunk(rb, uniform_i64(sp.re[cs.s_begin & 1][m1]) - rb, pc, pl);
+    }
     for (int64_t s = cs.s_begin; s < cs.n_steps; ++s) {
         const int pb = (int)(s & 1);
         const double T = sched.at(s, cs.n_steps, J.n_stages);
@@ -1073,28 +1092,36 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
         int32_t np = 0;
         double ndel = 0.0;
         if (book && more) np = draw(s + 1, lane, &ndel);
-        // this workgroup's estimates, one wavefront each
-        for (int j = wave;; j += NW) {
-            const int m = g + G * j;
-            if (m >= M) break;
+        // this workgroup's estimates: the wavefront's first one from the
+        // prefetched chunk, then its other chunks and estimates
+        auto score = [&](int m, bool first) {
             const int64_t b = uniform_i64(sp.rb[pb][m]), len = uniform_i64(sp.re[pb][m]) - b;
             const Real dr = (Real)uniform_f64(sp.d[pb][m]);
             Real acc = 0;
-            for (int64_t o = lane; o < len; o += (int64_t)kWave * U) {
-                int32_t cc[U];
-                Real ll[U];
+            int64_t o = 0;
+            if (first) {
+                Real rr[U];
+#pragma unroll
+                for (int c = 0; c < U; ++c) rr[c] = r[rpos_g(J, pc[c])];
 #pragma unroll
                 for (int c = 0; c < U; ++c) {
-                    const int64_t q = b + (o + c * kWave < len ? o + c * kWave : 0);
-                    cc[c] = J.col[q];
-                    ll[c] = (Real)lenp[q];
+                    if (lane + c * kWave < len) {
+                        const Real t = dr * pl[c];
+                        acc = fma(t, (Real)2 * rr[c] + t, acc);
+                    }
                 }
+                o = (int64_t)kWave * U;
+            }
+            for (; o < len; o += (int64_t)kWave * U) {
+                int32_t cc[U];
+                Real ll[U];
+                row_chunk(b + o, len - o, cc, ll);
                 Real rr[U];
 #pragma unroll
                 for (int c = 0; c < U; ++c) rr[c] = r[rpos_g(J, cc[c])];
 #pragma unroll
                 for (int c = 0; c < U; ++c) {
-                    if (o + c * kWave < len) {
+                    if (o + lane + c * kWave < len) {
                         const Real t = dr * ll[c];
                         acc = fma(t, (Real)2 * rr[c] + t, acc);
                     }
@@ -1105,6 +1132,12 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
                 sh.S[m] = S;
                 split_publish(X, s, m, S);
             }
+        };
+        if (m1 < M) score(m1, true);
+        for (int j = wave + NW;; j += NW) {
+            const int m = g + G * j;
+            if (m >= M) break;
+            score(m, false);
         }
         // step s + 1's row offsets and image values, in flight during the
         // exchange; then the other workgroups' sums
@@ -1115,6 +1148,9 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
             ne = J.row_ptr[np + 1];
             nfo = J.f[np];
         }
+        const double co = sqrt(cs.sse / KU);
+        const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
+        const double lnN1 = log(N1), invT = 1.0 / T;
         if (wave == 0) {
             bool need = lane < M && lane % G != g;
             const uint64_t want = split_stamp(s);
@@ -1136,14 +1172,24 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        const double co = sqrt(cs.sse / KU);
-        const double N1 = unit53(philox4x64(J.seed, J.chain_id, (uint64_t)s, 0, 1, 0).w0);
-        const double lnN1 = log(N1), invT = 1.0 / T;
+        if (book && more) {
+            sp.p[pb ^ 1][lane] = np;
+            sp.rb[pb ^ 1][lane] = nb;
+            sp.re[pb ^ 1][lane] = ne;
+        }
         __syncthreads();
         if (sp.fail) {
             cs.status = PILA_ETIMEDOUT;
             cs.n_steps = 0;
             break;
+        }
+        // step s + 1's first chunk, in flight while this step's change is
+        // applied
+        int32_t qc[U];
+        Real ql[U];
+        if (m1 < M && more) {
+            const int64_t rb = uniform_i64(sp.rb[pb ^ 1][m1]);
+            row_chunk(rb, uniform_i64(sp.re[pb ^ 1][m1]) - rb, qc, ql);
         }
         const Decision dn = decide(sh.S, M, lane, cs.sse, co, KU, T, invT, N1, lnN1);
         const double d_star = uniform_f64(sp.d[pb][dn.ms]);
@@ -1168,11 +1214,13 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
         if (book && more) {
             const double fo = change && np == pstar ? fnstar : nfo;
             const double fn = propose(s + 1, lane, fo, ndel);
-            sp.p[pb ^ 1][lane] = np;
             sp.fn[pb ^ 1][lane] = fn;
             sp.d[pb ^ 1][lane] = fn - fo;
-            sp.rb[pb ^ 1][lane] = nb;
-            sp.re[pb ^ 1][lane] = ne;
+        }
+#pragma unroll
+        for (int c = 0; c < U; ++c) {
+            pc[c] = qc[c];
+            pl[c] = ql[c];
         }
         if (f32 && J.resync_every > 0 && cs.since >= J.resync_every) {
             __syncthreads();
