@@ -1196,13 +1196,28 @@ __device__ void run_chain_split(const ChainJob& J, const SplitX& X, int g, Split
         const bool change = dn.accept && d_star != 0.0;
         int32_t pstar = 0;
         double fnstar = 0.0;
-        // Eq. 6 on this workgroup's copies (one entry per thread)
+        // Eq. 6 on this workgroup's copies, up to kSc entries per thread at
+        // once: all their loads, then all their stores (a row's rays are
+        // distinct, so the entries do not alias)
         if (change) {
             const int64_t b = uniform_i64(sp.rb[pb][dn.ms]), e = uniform_i64(sp.re[pb][dn.ms]);
             const Real dr = (Real)d_star;
-            for (int64_t q = b + threadIdx.x; q < e; q += blockDim.x) {
-                const uint32_t at = rpos_g(J, J.col[q]);
-                r[at] = r[at] + dr * (Real)lenp[q];
+            constexpr int kSc = 8;
+            const int64_t nt = blockDim.x;
+            for (int64_t q0 = b + threadIdx.x; q0 < e; q0 += nt * kSc) {
+                uint32_t at[kSc];
+                Real lv[kSc], rv[kSc];
+#pragma unroll
+                for (int k = 0; k < kSc; ++k) {
+                    const int64_t q = q0 + k * nt < e ? q0 + k * nt : q0;
+                    at[k] = rpos_g(J, J.col[q]);
+                    lv[k] = (Real)lenp[q];
+                }
+#pragma unroll
+                for (int k = 0; k < kSc; ++k) rv[k] = r[at[k]];
+#pragma unroll
+                for (int k = 0; k < kSc; ++k)
+                    if (q0 + k * nt < e) r[at[k]] = rv[k] + dr * lv[k];
             }
             pstar = uniform_i32(sp.p[pb][dn.ms]);
             fnstar = uniform_f64(sp.fn[pb][dn.ms]);
