@@ -220,6 +220,14 @@ typedef struct sat_trace {
 int32_t sat_workspace_size(const pila_geom* geom, const sat_params* params, size_t* bytes);
 
 /*
+ * sat_workspace_min - the smallest workspace sat_run accepts: the chain
+ * state alone (residual, per-tile sums, carry, statistics).  With it the
+ * pipelined body forms slot words in place and chains that would be split
+ * run on one workgroup (the general body); results are the same bits.
+ */
+int32_t sat_workspace_min(const pila_geom* geom, const sat_params* params, size_t* bytes);
+
+/*
  * sat_run - one SAT chain.  From the starting image d_image (N*N, updated
  * in place) and the measured sinogram d_sino (Pm, U*K):
  *   r = A f - Pm and its sum of squares (Eq. 1, Eq. 4);

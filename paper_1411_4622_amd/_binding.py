@@ -26,7 +26,8 @@ PROPOSALS = {"clamp": 0, "redraw": 1}                # PILA_PROP_*
 BODY_PIPED, BODY_LONG, BODY_GENERAL, BODY_SPLIT = 1, 2, 3, 4  # PILA_BODY_* kinds
 BODY_GLOBAL_R, BODY_SEGMENTED = 16, 32                # PILA_BODY_* flags
 
-EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size", "sat_run", "sat_run_static",
+EXPORTED = ["pila_build_scratch_size", "pila_build", "pila_forward", "pila_backproject", "sat_workspace_size",
+            "sat_workspace_min", "sat_run", "sat_run_static",
             "sat_batch_workspace_size", "sat_run_batch", "sat_graph_create", "sat_batch_graph_create",
             "sat_graph_launch", "sat_graph_stats", "sat_graph_destroy", "sirt_workspace_size", "sirt_run",
             "sirt_seq_workspace_size", "sirt_seq_run", "sat_drt_workspace_size", "sat_drt_run",
@@ -138,6 +139,7 @@ def load(path: str = LIB_PATH):
     lib.pila_forward.argtypes = [G, CS, V, V, V]
     lib.pila_backproject.argtypes = [G, CS, V, V, V]
     lib.sat_workspace_size.argtypes = [G, C.POINTER(CSatParams), C.POINTER(C.c_size_t)]
+    lib.sat_workspace_min.argtypes = [G, C.POINTER(CSatParams), C.POINTER(C.c_size_t)]
     lib.sat_run.argtypes = [G, CS, V, C.POINTER(CSatParams), V, V, C.c_size_t,
                             C.POINTER(CSatStats), C.POINTER(CSatTrace), V]
     lib.sat_run_static.argtypes = [G, CS, V, C.POINTER(CSatParams), V, C.POINTER(CSatStats),
@@ -347,11 +349,14 @@ def _stats_dict(s: CSatStats) -> dict:
     return {k: getattr(s, k) for k, _ in CSatStats._fields_}
 
 
-def sat_workspace(geom: Geometry, params: SatParams, device=None):
+def sat_workspace(geom: Geometry, params: SatParams, device=None, minimal: bool = False):
+    """sat_run's workspace: sat_workspace_size bytes, or with minimal=True
+    sat_workspace_min (the chain state alone)."""
     torch = _torch()
     n = C.c_size_t(0)
     p = params.c()
-    _check(load().sat_workspace_size(C.byref(geom.c), C.byref(p), C.byref(n)))
+    fn = load().sat_workspace_min if minimal else load().sat_workspace_size
+    _check(fn(C.byref(geom.c), C.byref(p), C.byref(n)))
     return torch.empty(int(n.value), dtype=torch.uint8, device=device or "cuda")
 
 

@@ -713,6 +713,15 @@ extern "C" int32_t sat_workspace_size(const pila_geom* geom, const sat_params* p
     return PILA_OK;
 }
 
+extern "C" int32_t sat_workspace_min(const pila_geom* geom, const sat_params* params, size_t* bytes)
+{
+    clear_error();
+    PILA_TRY(check_geom(geom));
+    if (!params || !bytes) return fail(PILA_EINVAL, "params or bytes is NULL");
+    *bytes = chain_bytes(geom, params);
+    return PILA_OK;
+}
+
 // One chain on the workspace d_ws (ws_bytes, at least chain_bytes; the
 // slot words go after the chain state when there is room).  timed: HIP
 // events around each chain-kernel launch (they are created per call).

@@ -148,6 +148,19 @@ def test_workspace_sizes(P):
     p64 = P.SatParams(n_steps=1, precision="f64").c()
     assert lib.sat_workspace_size(C.byref(g.c), C.byref(p64), C.byref(n)) == 0
     assert n.value >= 90 * 64 * 8
+    # the smallest workspace is the chain state; the full one adds room for
+    # a split chain's 15 residual and image copies when the residual may not
+    # fit in LDS and M >= 4 (here 90 x 64 x 8 bytes = 45 KB: it fits)
+    lo = C.c_size_t(0)
+    assert lib.sat_workspace_min(C.byref(g.c), C.byref(p64), C.byref(lo)) == 0
+    assert 90 * 64 * 8 <= lo.value <= n.value
+    big = _geom(P, n=256, U=720, K=363)
+    p32 = P.SatParams(n_steps=1, precision="f32", m_cand=32).c()
+    assert lib.sat_workspace_min(C.byref(big.c), C.byref(p32), C.byref(lo)) == 0
+    assert lib.sat_workspace_size(C.byref(big.c), C.byref(p32), C.byref(n)) == 0
+    r_bytes = 720 * 368 * 4
+    assert n.value - lo.value >= 15 * (r_bytes + 256 * 256 * 8)
+    assert lib.sat_workspace_min(None, C.byref(p32), C.byref(lo)) == P._binding.PILA_EINVAL
     sp = CSirtParams(10, 0, 0.1)
     assert lib.sirt_workspace_size(C.byref(g.c), C.byref(sp), C.byref(n)) == 0
     assert n.value >= 2 * 90 * 64 * 8

@@ -207,16 +207,27 @@ def test_batch_matches_single_and_oracle(P):
 def test_segmented_general_body_matches_in_group(P):
     """An FP32 chain the pipelined body cannot take (M = 40, 360 angles) with a
     residual too large for LDS: sat_run runs it in segments with grid-wide
-    resyncs, the general batch kernel resyncs inside its workgroup; both must
+    resyncs (on one workgroup with the smallest workspace, else split over
+    ten), the general batch kernel resyncs inside its workgroup; all must
     give the same bits."""
     sl = _slice(96, 360, 136, seed=61, masked=True, I0=1e4)
     assert 360 * 136 * 4 > 160 * 1024
     prm = P.SatParams(n_steps=3000, seed=17, m_cand=40, T0=None, q_auto=30, precision="f32",
                       resync_every=200, n_stages=20)
-    f_seg, st_seg, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
-    assert st_seg["resyncs"] >= 2 and st_seg["chain_launches"] > 1
     geom = P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32")
     pl = P.pila_build(geom)
+    sino = torch.from_numpy(sl.sino).cuda()
+    # the smallest workspace leaves no room for a split chain's copies
+    img_seg = torch.from_numpy(sl.f0.copy()).cuda()
+    st_seg, _ = P.sat_run(pl, sino, prm, img_seg, workspace=P.sat_workspace(geom, prm, minimal=True))
+    f_seg = img_seg.cpu().numpy()
+    assert st_seg["body"] & 0xff == (P._binding.BODY_GENERAL | P._binding.BODY_GLOBAL_R
+                                     | P._binding.BODY_SEGMENTED), st_seg["body"]
+    assert st_seg["resyncs"] >= 2 and st_seg["chain_launches"] > 1
+    # with room for them the chain is split over workgroups: same bits
+    f_split, st_split, _ = _gpu_chain(P, sl, "f32", prm, trace=False)
+    assert st_split["body"] & 15 == P._binding.BODY_SPLIT, st_split["body"]
+    assert np.array_equal(f_split, f_seg) and st_split["accepts"] == st_seg["accepts"]
     img = torch.from_numpy(sl.f0.copy()).cuda()
     st = P.sat_run_batch([P.Job(pl, torch.from_numpy(sl.sino).cuda(), img, prm)],
                          waves_per_chain=16, chains_per_cu=1)
