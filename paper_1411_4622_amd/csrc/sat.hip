@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kPipedThreads) void sat_piped_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_piped<Real, RLDS, CPW, E, false, TK, LenT>(job, lds, sh, false);
+    run_chain_piped<Real, RLDS, CPW, E, false, TK, LenT, true>(job, lds, sh, false);
 }
 
 // one segment of a chain whose FP64 resyncs run grid-wide between segments
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kPipedThreads) void sat_segment_kernel(ChainJob job
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_piped<float, false, CPW, E, false, TK, LenT>(job, lds, sh, true);
+    run_chain_piped<float, false, CPW, E, false, TK, LenT, true>(job, lds, sh, true);
 }
 
 // the slot word (ray_slot) of every PILA entry, for the TK kernels
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kPipedThreads) void sat_long_kernel(ChainJob job)
 {
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
-    run_chain_long<Real, RLDS, E, false, LenT>(job, lds, sh, false);
+    run_chain_long<Real, RLDS, E, false, LenT, true>(job, lds, sh, false);
 }
 
 // one segment of a long-row chain whose FP64 resyncs run grid-wide between segments
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kPipedThreads) void sat_long_segment_kernel(ChainJo
     extern __shared__ __align__(16) char lds[];
     __shared__ ChainShared sh;
     if (job.carry->done || job.carry->status != PILA_OK) return;
-    run_chain_long<float, false, E, false, LenT>(job, lds, sh, true);
+    run_chain_long<float, false, E, false, LenT, true>(job, lds, sh, true);
 }
 
 // one segment of a general-body chain (FP32, residual in global memory)

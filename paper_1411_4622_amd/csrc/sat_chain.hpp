@@ -38,6 +38,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -1264,6 +1265,30 @@ __device__ __forceinline__ void st32(T* base, uint32_t i, T v)
     *(T*)((char*)base + i * (uint32_t)sizeof(T)) = v;
 }
 
+// A length loaded a step or two before it is used: FP32 lengths as they are;
+// one-byte lengths as the raw byte in the register's bits, read back (q/180,
+// an ALU operation on the loaded value, len_use) once the load has arrived,
+// so that nothing waits for it when it is issued.
+template <typename Real, typename LenT>
+__device__ __forceinline__ Real len_hold(const LenT* lenp, uint32_t at)
+{
+    if constexpr (std::is_same<LenT, LenQ>::value && std::is_same<Real, float>::value)
+        return __uint_as_float((uint32_t)ld32((const uint8_t*)lenp, at));
+    else
+        return (Real)ld32(lenp, at);
+}
+template <typename Real, typename LenT>
+__device__ __forceinline__ Real len_use(Real v)
+{
+    if constexpr (std::is_same<LenT, LenQ>::value && std::is_same<Real, float>::value) {
+        LenQ q;
+        q.q = (uint8_t)__float_as_uint(v);
+        return (Real)(float)q;
+    } else {
+        return v;
+    }
+}
+
 // Where the residual value of ray g lives in the pipelined body's global
 // mode: the LDS part (angles u < UL, bins k_lo .. k_lo + Kc - 1) as
 // kRaySlotLds | index, else u << 22 | its position in the tiled global
@@ -1336,7 +1361,12 @@ __device__ void lds_residual_store(const ChainJob& J, Real* r, const Real* rl)
 // TK: the rows' slot words come precomputed from J.tcol (loaded instead of
 // the ray indices, which are formed back from them where a global residual
 // value is read or written)
-template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false, bool TK = false, typename LenT = Real>
+// LATE: one-byte lengths are held raw and read back where used (lone
+// chains: reading them back at the load made the step wait for it);
+// otherwise at the load (batches, where the compiler places that better).
+// Either way the same float results.
+template <typename Real, bool RLDS, int CPW, int E, bool SERVED = false, bool TK = false, typename LenT = Real,
+          bool LATE = false>
 __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int LPC = kWave / CPW;  // lanes per estimate
@@ -1442,7 +1472,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                 S.tk[e] = ld32(J.tcol, at);
             else
                 S.col[e] = ld32(J.col, at);
-            S.len[e] = (Real)ld32(lenp, at);
+            S.len[e] = LATE ? len_hold<Real, LenT>(lenp, at) : (Real)ld32(lenp, at);
         }
     };
     // where each ray of a row lives: LDS index (flagged) or patch-table slot
@@ -1461,6 +1491,10 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
     auto in_lds = [&](int tk) { return !RLDS && (tk & kLdsFlag) != 0; };
     // residual value at a position of the global residual, or of ray g in LDS
     auto rget = [&](uint32_t g) -> Real { return RLDS ? r[g] : ld32((const Real*)r, g); };
+    auto lenv = [&](Real v) -> Real {
+        if constexpr (LATE) return len_use<Real, LenT>(v);
+        return v;
+    };
 
     RowSet<Real, E> A, B, C;
     prefetch(A, s_begin);
@@ -1507,7 +1541,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
         for (int k = 0; k < CPW; ++k) part[k] = (Real)0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const Real t = (li + e * LPC < X.n) ? dr * X.len[e] : (Real)0;
+            const Real t = (li + e * LPC < X.n) ? dr * lenv(X.len[e]) : (Real)0;
             part[e % CPW] = fma(t, (Real)2 * X.rv[e] + t, part[e % CPW]);
         }
         const Real S = canon_sum<LPC>(part);
@@ -1537,7 +1571,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (li + e * LPC < X.n) {
-                    const Real rn = X.rv[e] + dr * X.len[e];
+                    const Real rn = X.rv[e] + dr * lenv(X.len[e]);
                     if (RLDS) {
                         r[X.col[e]] = rn;
                     } else if (X.tk[e] & kLdsFlag) {
@@ -1655,7 +1689,7 @@ struct LongRow {
     double delta, N1, lnN1;
 };
 
-template <typename Real, bool RLDS, int E, bool SERVED = false, typename LenT = Real>
+template <typename Real, bool RLDS, int E, bool SERVED = false, typename LenT = Real, bool LATE = false>
 __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bool segmented)
 {
     constexpr int BL = kWave;  // steps per block of draws: lane j <-> step base + j
@@ -1734,7 +1768,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
             const int q = lane + e * kWave;
             const uint32_t at = q < S.n ? b + (uint32_t)q : 0u;
             S.col[e] = ld32(J.col, at);
-            S.len[e] = (Real)ld32(lenp, at);
+            S.len[e] = LATE ? len_hold<Real, LenT>(lenp, at) : (Real)ld32(lenp, at);
         }
     };
     // residual value of ray g: LDS part (angles u < UL: *lidx its index) or
@@ -1768,6 +1802,10 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
         int li[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) rv[e] = rget(X.col[e], &li[e]);
+        // (LATE) the lengths read back while the gathers are in flight
+        Real ln[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) ln[e] = LATE ? len_use<Real, LenT>(X.len[e]) : X.len[e];
         const double fo = J.f[X.p];
         double fn = fo + X.delta;
         if (fn < J.f_min) fn = J.f_min;
@@ -1777,7 +1815,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
         Real part[1] = {(Real)0};
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const Real t = (lane + e * kWave < X.n) ? dr * X.len[e] : (Real)0;
+            const Real t = (lane + e * kWave < X.n) ? dr * ln[e] : (Real)0;
             part[0] = fma(t, (Real)2 * rv[e] + t, part[0]);
         }
         // entries beyond the registers (rows longer than 64 E), read in
@@ -1802,7 +1840,7 @@ __device__ void run_chain_long(const ChainJob& J, char* lds, ChainShared& sh, bo
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 if (lane + e * kWave < X.n) {
-                    const Real rn = rv[e] + dr * X.len[e];
+                    const Real rn = rv[e] + dr * ln[e];
                     if (RLDS)
                         r[X.col[e]] = rn;
                     else if (li[e] >= 0)

@@ -1,6 +1,7 @@
 """HIP graphs of chains and batches against the eager calls (MI355X).
 
-A graph captured from sat_run (a segmented FP32 chain: hundreds of launches)
+A graph captured from sat_run (a segmented FP32 chain: hundreds of launches;
+chains on one workgroup and split over several)
 or from sat_run_batch (several groups on forked streams) is replayed several
 times, with other eager work and synchronisations between the replays, and
 every replay must give the eager call's bits."""
@@ -29,7 +30,10 @@ def _eager_noise():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("dt,N,U,K,M,every", [("f32", 192, 180, 272, 8, 256), ("f64", 40, 36, 57, 16, 0)])
+# the last two: chains split over eight workgroups (their exchange words are
+# cleared by a kernel at the start of every replay)
+@pytest.mark.parametrize("dt,N,U,K,M,every", [("f32", 192, 180, 272, 8, 256), ("f64", 40, 36, 57, 16, 0),
+                                              ("f32", 64, 600, 91, 32, 300), ("f64", 48, 600, 68, 32, 0)])
 def test_chain_graph_replays_match_eager(P, dt, N, U, K, M, every):
     sl = _slice(N, U, K, seed=N + 1, masked=True, I0=1e4)
     prm = P.SatParams(n_steps=12000, seed=5, chain_id=2, m_cand=M, T0=None, q_auto=40, precision=dt,
