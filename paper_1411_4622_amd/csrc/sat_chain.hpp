@@ -1519,6 +1519,19 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
                     __attribute__((always_inline)) -> bool {
         const double T = sched.at(s, n_steps, J.n_stages);
         const double invT = sched.invT;
+        // next step's global operands, issued before this step is scored so
+        // that they have the whole step to arrive (the residual already holds
+        // step s - 1's change; step s's is patched in at step s + 1); every
+        // entry is written, so the set's values of two steps ago die here
+        table_slots(Y);
+        if (!RLDS) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                Y.rv[e] = (Real)0;
+                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = rget(gcol(Y, e));
+            }
+        }
+        Y.fo = J.f[Y.p];
         if (!RLDS && patch) {  // the previous step's accepted change
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -1549,17 +1562,7 @@ __device__ void run_chain_piped(const ChainJob& J, char* lds, ChainShared& sh, b
             sh.S[m_mine] = (double)S;
             sh.d[m_mine] = d;
         }
-        // next step's global operands (issued before the row loads of step s + 2)
-        table_slots(Y);
-        if (!RLDS) {
-            // every entry is written, so the set's values of two steps ago die here
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                Y.rv[e] = (Real)0;
-                if (!(Y.tk[e] & kLdsFlag)) Y.rv[e] = rget(gcol(Y, e));
-            }
-        }
-        Y.fo = J.f[Y.p];
+        // the rows of step s + 2
         prefetch(Z, s + 2);
         if (SERVED) cancel_probe(J, sh, s);
         __syncthreads();
