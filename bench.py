@@ -70,10 +70,10 @@ def chain_bytes(n_steps: int, M: int, f_mean: float, accepts: int, len_bytes: in
 TRAFFIC_SOURCES = ("paper_1411_4622_amd/csrc/sat_chain.hpp", "paper_1411_4622_amd/csrc/sat.hip",
                    "paper_1411_4622_amd/csrc/common.hpp", "bench_workloads.py")
 TRAFFIC = {"kernel": "sat_batch_kernel<float,1,8>",
-           "sources_sha256": "d90eb590d67c4c76827ee8367b6dd45cd90bb7aac2ab7fff2591290929cf2dc4",
-           "fetch_kib": 9651081035.0625, "fetch_factor": 524288.0 / 262155.5,
-           "write_kib": 1117738611.40625, "write_factor": 1.0,
-           "bytes_per_dispatch": 9651081035.0625 * 1024 * (524288.0 / 262155.5) + 1117738611.40625 * 1024 * 1.0,
+           "sources_sha256": "b70ca5d2de377365d7b6ceebbfdd3ddfd87111ddc20a1f37e16a83d509f7cdcc",
+           "fetch_kib": 9659812400.5625, "fetch_factor": 524288.0 / 262155.5,
+           "write_kib": 1120302595.90625, "write_factor": 524288.0 / 524288.0,
+           "bytes_per_dispatch": 9659812400.5625 * 1024 * (524288.0 / 262155.5) + 1120302595.90625 * 1024 * (524288.0 / 524288.0),
            "profile": "profiles/sat_batch_kernel_c3_512slices.md"}
 
 
