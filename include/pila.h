@@ -272,7 +272,8 @@ int32_t sat_run(const pila_geom* geom, const pila_csr* csr, const double* d_sino
  * is a static device array of PILA_STATIC_SCRATCH_BYTES that the library
  * holds on each GPU it runs on until the process ends; the call allocates
  * nothing.  Same arguments, semantics and results as sat_run (the slot
- * words go into the array when they fit after the chain state; the
+ * words, or a split chain's copies and exchange words, go into the array
+ * when they fit after the chain state; the
  * statistics carry no kernel timing: chain_kernel_ms = 0).  Every call on a
  * GPU shares that GPU's array, so calls that overlap on one GPU (other
  * streams, other threads) race and give wrong results; each call writes
