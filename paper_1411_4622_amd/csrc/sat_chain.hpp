@@ -968,8 +968,10 @@ __device__ void run_chain_simple(const ChainJob& J, char* lds, ChainShared& sh, 
 // The estimates' pixels, changes and row offsets do not depend on the chain
 // state: wavefront 0 draws all M of them one step ahead (one lane each), the
 // image value with them, patched when the step in between changes that
-// pixel, so the scoring wavefronts read them from LDS.  Sums are the
-// canonical ones (one wavefront per estimate, U entries per lane in flight).
+// pixel, so the scoring wavefronts read them from LDS; each wavefront loads
+// the first chunk of its next row (indices and lengths) after the decision,
+// while the accepted change is applied.  Sums are the canonical ones (one
+// wavefront per estimate, U entries per lane in flight).
 // The chain state comes from the carry (segments end at FP32 resyncs, which
 // run grid-wide on group 0's copy and are then copied to the others).
 // ---------------------------------------------------------------------------
