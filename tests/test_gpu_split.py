@@ -92,6 +92,35 @@ def test_split_fp32_equals_batch_general_body(P, dtype):
     assert st_a["max_drift_r"] <= 1e-3
 
 
+def test_split_full_size_equals_general_body(P):
+    """The large-slice workload's chain (1024 x 1024, 720 angles, 1449 bins,
+    M = 32, its seeds and schedule), 2000 steps with resyncs every 500
+    nonzero changes: split over eight workgroups as sat_run runs it (the
+    launch the benchmark times) and on one workgroup in a batch give the same
+    bits; the FP32 residual stays within 1e-3 of the FP64 rebuilds."""
+    import datagen
+    c = datagen.CONFIGS["c4"]
+    sl = datagen.config_slice("c4")
+    prm = P.SatParams(n_steps=2000, seed=c["chain_seed"], chain_id=0, n_stages=c["n_stages"],
+                      m_cand=c["M"], T0=None, q_auto=c["q_auto"], tn_ratio=c["tn_ratio"],
+                      delta_max=c["delta_max"], precision="f32", resync_every=500)
+    pl = P.pila_build(P.Geometry(sl.N, sl.angles, sl.K, sl.mask, "f32"))
+    sino = torch.from_numpy(sl.sino).cuda()
+    print("fp32 split full size 1024x1024 U=720 M=32", flush=True)
+    img_a = torch.from_numpy(sl.f0.copy()).cuda()
+    st_a, _ = P.sat_run(pl, sino, prm, img_a)
+    assert _split_body(P, st_a, 32) and (st_a["body"] >> 8) & 0xff == 8, st_a["body"]
+    assert st_a["resyncs"] >= 2 and st_a["status"] == 0
+    img_b = torch.from_numpy(sl.f0.copy()).cuda()
+    st_b = P.sat_run_batch([P.Job(pl, sino, img_b, prm)], waves_per_chain=16, chains_per_cu=1)
+    assert st_b[0]["body"] & 15 == P._binding.BODY_GENERAL
+    torch.cuda.synchronize()
+    assert torch.equal(img_a, img_b)
+    for k in ("accepts", "accepts_nonzero", "resyncs"):
+        assert st_a[k] == st_b[0][k], k
+    assert st_a["max_drift_r"] <= 1e-3
+
+
 def test_split_wait_limit_ends_chain(P):
     """With a wait limit of zero a workgroup gives up as soon as a sum it
     needs has not arrived: the chain ends with PILA_ETIMEDOUT and every
