@@ -180,7 +180,8 @@ typedef struct sat_params {
     int32_t schedule;     /* PILA_SCHED_LINEAR, _EXP or _CUBIC */
     int32_t proposal;     /* PILA_PROP_CLAMP or PILA_PROP_REDRAW (redraws use counter
                              (s, m, 0, j) for the j-th redraw, at most 256, after which
-                             the value stays; chains that redraw run the general body) */
+                             the value stays; chains that redraw run the general or
+                             split body) */
 } sat_params;
 
 typedef struct sat_stats {
